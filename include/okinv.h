@@ -1,0 +1,157 @@
+/*
+ * okinv.h -- C-ABI of the MI355X (gfx950) Oktay-Kronfeld operator and inverter.
+ *
+ * The library applies the rewritten OK Dirac operator
+ *
+ *   (M psi)_x = mhat psi_x + sum_{k=0}^{26} W_{k,x} psi_{x+d_k}           (Eq. minFlopForm)
+ *
+ * with the 12x12 spin-colour precalculation matrices W (Sec. 2.2,
+ * Eqs. shifted_W_first..shifted_W_last) built once per gauge field, and solves
+ * M psi = xi (Eq. dslash) by BiCGStab (Sec. 2.3).
+ *
+ * Conventions shared by every call:
+ *   - Geometry: L = (Lx, Ly, Lz, Lt), every L >= 3, periodic in all four
+ *     directions; direction mu = 0..3 is x, y, z, t (the paper's mu = 4 is t).
+ *     Site index s = x + Lx*(y + Ly*(z + Lz*t)); V = Lx*Ly*Lz*Lt < 2^31 / 64.
+ *   - Complex numbers are (re, im) pairs of the stated real type.
+ *   - Links: d_links is FP64 complex [V][4][3][3] (row-major colour), the link
+ *     U_mu(x) from x to x+mu (it multiplies psi_{x+mu}).
+ *   - Spinors: [nrhs][V][4 spin][3 colour] complex, FP64 or FP32; the
+ *     spin-colour index is 3*alpha + a; the spin basis is the one in which the
+ *     paper writes W (gamma_4 = diag(1,1,-1,-1), gamma_i = [[0,s_i],[s_i,0]]).
+ *   - The 27 offsets d_k in storage order: k=0: 0; 1..4: +mu; 5..8: -mu;
+ *     9..11: +2i; 12..14: -2i; 15..17: +i+j (ij = xy,xz,yz); 18..20: -i-j;
+ *     21..23: +i-j; 24..26: -i+j.
+ *   - Device pointers are hipMalloc'ed by the caller, 16-byte aligned at least
+ *     (256 recommended).  The caller owns and frees every buffer (W, scratch,
+ *     workspace); the library allocates no device memory and keeps no pointer
+ *     after a call returns.  `stream` is a hipStream_t (NULL: default stream).
+ *   - Every call validates its arguments on the host before any HIP call and
+ *     returns an ok_status; on error ok_last_error() holds a message.
+ */
+#ifndef OKINV_H
+#define OKINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OKINV_ABI_VERSION 1
+
+/* Status codes.  0 success, > 0 solver outcomes (stats filled), < 0 errors. */
+enum ok_status {
+    OK_SUCCESS = 0,
+    OK_NOT_CONVERGED = 1,   /* max_iter reached; stats hold the last residual   */
+    OK_BREAKDOWN = 2,       /* BiCGStab breakdown persisted through restarts     */
+    OK_EINVAL = -1,         /* bad geometry, nrhs, null/aliasing pointer, precision */
+    OK_ESIZE = -2,          /* a buffer or workspace is smaller than required    */
+    OK_EALIGN = -3,         /* a device pointer is not 16-byte aligned            */
+    OK_EDEVICE = -4,        /* a HIP runtime error; message in ok_last_error()    */
+    OK_ENONFINITE = -5      /* NaN/Inf met in the source or a residual            */
+};
+
+/* Storage / arithmetic precision of W and of spinors. */
+enum ok_prec { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2 };
+
+typedef struct ok_geom {
+    int32_t L[4];           /* Lx, Ly, Lz, Lt */
+} ok_geom;
+
+/* Coefficients of the tree-level tadpole-improved OK operator as they appear
+ * in Eqs. shifted_W_first..last.  mhat = u0/(2 kappa) is the identity part of
+ * W0; the paper applies it separately from the stored W0 (footnote in
+ * Sec. 2.2), so W does not depend on mhat. */
+typedef struct ok_coeffs {
+    double mhat, u0, zeta, r_s, c_B, c_E, c_EE, c_1, c_2, c_3, c_4, c_5;
+} ok_coeffs;
+
+typedef struct ok_solver_params {
+    double tol;             /* stop when ||xi - M psi|| / ||xi|| <= tol in FP64 (e.g. 1e-10) */
+    double delta;           /* reliable-update threshold of the low-precision solve (e.g. 0.1) */
+    int32_t max_iter;       /* BiCGStab iterations, all restarts included       */
+    int32_t max_restarts;   /* restarts after breakdown or residual drift        */
+    int32_t zero_guess;     /* 1: start from psi = 0; 0: use d_psi as the guess  */
+    int32_t verbose;        /* 1: print one line per iteration to stderr         */
+} ok_solver_params;
+
+typedef struct ok_solver_stats {
+    int32_t status;         /* ok_status of this right-hand side                 */
+    int32_t iterations;     /* BiCGStab iterations                               */
+    int32_t matvec_hi;      /* FP64 applications of M                            */
+    int32_t matvec_lo;      /* low-precision applications of M                   */
+    int32_t reliable_updates;
+    int32_t restarts;
+    double true_rel_resid;  /* ||xi - M64 psi|| / ||xi||, FP64, at return       */
+    double seconds;         /* wall time of the call                             */
+} ok_solver_stats;
+
+/* ABI version of this header and of the private W layout. */
+int ok_abi_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* ok_last_error(void);
+
+/* Bytes of the W buffer for precision prec (OK_F64, OK_F32 or OK_BF16):
+ * 27 blocks x 144 complex x sizeof(complex) per site, site stride padded to a
+ * multiple of 64.  The layout is private to the library (versioned by
+ * ok_abi_version). */
+int ok_W_bytes(const ok_geom* g, int prec, size_t* bytes);
+
+/* Bytes of the scratch ok_precompute_W needs: the six clover planes F_{mu nu}
+ * (3x3 complex FP64) per site. */
+int ok_precompute_scratch_bytes(const ok_geom* g, size_t* bytes);
+
+/* Precalculation (Sec. 2.2): fill d_W with the 27 blocks W_{k,x} of every site
+ * from the links, in FP64 arithmetic, stored at precision prec.  The 14
+ * forward blocks follow Eqs. shifted_W_first..last; the 13 backward blocks
+ * are W_{-d,x} = gamma5 W_{+d,x-d}^dag gamma5 (Eqs. conjugate and
+ * opp_diag_pre_mat).  B_i and E_i are the clover fields of the links:
+ * F_{mu nu} = traceless part of (Q_{mu nu} - Q_{mu nu}^dag)/8 with Q the sum
+ * of the four counter-clockwise plaquette leaves at x, B_i = eps_ijk F_jk / 2,
+ * E_i = F_{ti}.  Asynchronous on `stream`.  Redo it when the links, u0 or any
+ * c changes; mhat alone does not need it. */
+int ok_precompute_W(const ok_geom* g, const ok_coeffs* c, const double* d_links,
+                    int prec, void* d_W, size_t W_bytes,
+                    void* d_scratch, size_t scratch_bytes, void* stream);
+
+/* d_out = M d_psi for nrhs right-hand sides (Eq. minFlopForm with mhat from c).
+ * Allowed (W_prec, spinor_prec): (F64, F64), (F32, F32), (BF16, F32).
+ * Arithmetic is FP64 for FP64 W and FP32 (FP32 accumulation) otherwise.
+ * d_out must not overlap d_psi.  Asynchronous on `stream`. */
+int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec,
+               const void* d_psi, void* d_out, int spinor_prec, int nrhs, void* stream);
+
+/* Expand d_W into dense FP64 blocks d_dense[V][27][12][12] complex (for
+ * inspection and tests).  Asynchronous on `stream`. */
+int ok_W_to_dense(const ok_geom* g, const void* d_W, int prec, double* d_dense, void* stream);
+
+/* Workspace bytes of ok_bicgstab for nrhs right-hand sides; Wlo_prec < 0 means
+ * plain FP64 (no low-precision operator). */
+int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t* bytes);
+
+/* Solve M psi = xi for nrhs right-hand sides by BiCGStab (Sec. 2.3).
+ *   d_W64   FP64 W (always needed: residuals and the final check are FP64).
+ *   d_Wlo   NULL: plain FP64 BiCGStab.  Otherwise W at Wlo_prec (OK_F32 or
+ *           OK_BF16): the iteration runs in FP32 fields with that operator and
+ *           FP64 reliable updates (x accumulated and r recomputed in FP64 when
+ *           the low-precision residual drops by params->delta).
+ *   d_xi    FP64 source [nrhs][V][4][3] complex.
+ *   d_psi   FP64 [nrhs][V][4][3]: the initial guess unless params->zero_guess,
+ *           the solution on return.
+ *   d_work  workspace of ok_bicgstab_workspace_bytes bytes.
+ *   stats   host array of nrhs entries, filled for every right-hand side.
+ * Synchronous: returns after every right-hand side converged or failed.
+ * Returns OK_SUCCESS if all converged, else the first failing status. */
+int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
+                const void* d_W64, const void* d_Wlo, int Wlo_prec,
+                const double* d_xi, double* d_psi, int nrhs,
+                void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OKINV_H */

@@ -1,0 +1,226 @@
+// C-ABI entry points of libokinv: validation, size queries, precompute, apply.
+// Every argument is checked on the host before the first HIP call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+#include "kernels.h"
+#include "wlayout.h"
+
+namespace okinv {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+    set_error("HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what, file, line);
+    return OK_EDEVICE;
+}
+
+int make_geo(const ok_geom* g, Geo* out) {
+    if (!g) {
+        set_error("geometry is NULL");
+        return OK_EINVAL;
+    }
+    long v = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (g->L[mu] < 3 || g->L[mu] > 4096) {
+            set_error("lattice extent L[%d] = %d outside [3, 4096]", mu, g->L[mu]);
+            return OK_EINVAL;
+        }
+        v *= g->L[mu];
+        if (v > (1L << 28)) {
+            set_error("lattice volume exceeds 2^28 sites");
+            return OK_EINVAL;
+        }
+    }
+    for (int mu = 0; mu < 4; ++mu) out->L[mu] = g->L[mu];
+    out->V = (int)v;
+    out->Vs = (int)((v + 63) / 64 * 64);
+    return OK_SUCCESS;
+}
+
+int check_ptr(const void* p, const char* name) {
+    if (!p) {
+        set_error("%s is NULL", name);
+        return OK_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(p) % 16) {
+        set_error("%s is not 16-byte aligned", name);
+        return OK_EALIGN;
+    }
+    return OK_SUCCESS;
+}
+
+static int check_coeffs(const ok_coeffs* c) {
+    if (!c) {
+        set_error("coefficients are NULL");
+        return OK_EINVAL;
+    }
+    const double* v = &c->mhat;
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(v[i])) {
+            set_error("coefficient %d is not finite", i);
+            return OK_EINVAL;
+        }
+    if (!(c->u0 > 0.0)) {
+        set_error("u0 must be positive");
+        return OK_EINVAL;
+    }
+    return OK_SUCCESS;
+}
+
+static bool valid_prec(int p) { return p == OK_F64 || p == OK_F32 || p == OK_BF16; }
+
+static size_t spinor_bytes(const Geo& g, int sprec) { return (size_t)g.V * 12 * (sprec == OK_F64 ? 16 : 8); }
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+#define OK_TRY(expr)                 \
+    do {                             \
+        int _r = (expr);             \
+        if (_r != OK_SUCCESS) return _r; \
+    } while (0)
+
+}  // namespace okinv
+
+using namespace okinv;
+
+extern "C" {
+
+int ok_abi_version(void) { return OKINV_ABI_VERSION; }
+
+const char* ok_last_error(void) { return g_err; }
+
+int ok_W_bytes(const ok_geom* g, int prec, size_t* bytes) {
+    Geo G;
+    OK_TRY(make_geo(g, &G));
+    if (!valid_prec(prec)) {
+        set_error("unknown precision %d", prec);
+        return OK_EINVAL;
+    }
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return OK_EINVAL;
+    }
+    *bytes = w_bytes(prec, G.Vs);
+    return OK_SUCCESS;
+}
+
+int ok_precompute_scratch_bytes(const ok_geom* g, size_t* bytes) {
+    Geo G;
+    OK_TRY(make_geo(g, &G));
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return OK_EINVAL;
+    }
+    *bytes = (size_t)6 * 9 * 16 * G.Vs;
+    return OK_SUCCESS;
+}
+
+int ok_precompute_W(const ok_geom* g, const ok_coeffs* c, const double* d_links, int prec, void* d_W,
+                    size_t W_bytes, void* d_scratch, size_t scratch_bytes, void* stream) {
+    Geo G;
+    OK_TRY(make_geo(g, &G));
+    OK_TRY(check_coeffs(c));
+    if (!valid_prec(prec)) {
+        set_error("unknown precision %d", prec);
+        return OK_EINVAL;
+    }
+    OK_TRY(check_ptr(d_links, "d_links"));
+    OK_TRY(check_ptr(d_W, "d_W"));
+    OK_TRY(check_ptr(d_scratch, "d_scratch"));
+    if (W_bytes < w_bytes(prec, G.Vs)) {
+        set_error("W buffer has %zu bytes, needs %zu", W_bytes, w_bytes(prec, G.Vs));
+        return OK_ESIZE;
+    }
+    const size_t need = (size_t)6 * 9 * 16 * G.Vs;
+    if (scratch_bytes < need) {
+        set_error("scratch has %zu bytes, needs %zu", scratch_bytes, need);
+        return OK_ESIZE;
+    }
+    const size_t lb = (size_t)G.V * 4 * 9 * 16;
+    if (overlap(d_W, w_bytes(prec, G.Vs), d_links, lb) || overlap(d_scratch, need, d_links, lb) ||
+        overlap(d_W, w_bytes(prec, G.Vs), d_scratch, need)) {
+        set_error("d_W, d_scratch and d_links must not overlap");
+        return OK_EINVAL;
+    }
+    return launch_precompute(G, *c, d_links, prec, d_W, d_scratch, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// Threads per site of the single right-hand-side stencil (1, 2 or 4); the
+// environment variable OKINV_TPS overrides the default per precision.
+int okinv::stencil_tps(int Wprec) {
+    const char* e = getenv("OKINV_TPS");
+    const int over = e ? atoi(e) : 0;
+    if (over == 1 || over == 2 || over == 4) return over;
+    return Wprec == OK_F64 ? 2 : 1;
+}
+
+extern "C" {
+
+int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec, const void* d_psi, void* d_out,
+               int spinor_prec, int nrhs, void* stream) {
+    Geo G;
+    OK_TRY(make_geo(g, &G));
+    OK_TRY(check_coeffs(c));
+    if (!valid_prec(W_prec)) {
+        set_error("unknown W precision %d", W_prec);
+        return OK_EINVAL;
+    }
+    const bool ok_pair = (W_prec == OK_F64 && spinor_prec == OK_F64) ||
+                         (W_prec != OK_F64 && spinor_prec == OK_F32);
+    if (!ok_pair) {
+        set_error("unsupported (W_prec, spinor_prec) = (%d, %d)", W_prec, spinor_prec);
+        return OK_EINVAL;
+    }
+    if (nrhs < 1 || nrhs > 4096) {
+        set_error("nrhs = %d outside [1, 4096]", nrhs);
+        return OK_EINVAL;
+    }
+    OK_TRY(check_ptr(d_W, "d_W"));
+    OK_TRY(check_ptr(d_psi, "d_psi"));
+    OK_TRY(check_ptr(d_out, "d_out"));
+    const size_t sb = spinor_bytes(G, spinor_prec);
+    if (overlap(d_psi, sb * nrhs, d_out, sb * nrhs)) {
+        set_error("d_out must not overlap d_psi");
+        return OK_EINVAL;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int tps = stencil_tps(W_prec);
+    for (int r = 0; r < nrhs; ++r) {
+        const char* in = reinterpret_cast<const char*>(d_psi) + sb * r;
+        char* out = reinterpret_cast<char*>(d_out) + sb * r;
+        OK_TRY(launch_apply(G, d_W, W_prec, in, out, c->mhat, tps, EPI_NONE, nullptr, nullptr, st));
+    }
+    return OK_SUCCESS;
+}
+
+int ok_W_to_dense(const ok_geom* g, const void* d_W, int prec, double* d_dense, void* stream) {
+    Geo G;
+    OK_TRY(make_geo(g, &G));
+    if (!valid_prec(prec)) {
+        set_error("unknown precision %d", prec);
+        return OK_EINVAL;
+    }
+    OK_TRY(check_ptr(d_W, "d_W"));
+    OK_TRY(check_ptr(d_dense, "d_dense"));
+    return launch_to_dense(G, d_W, prec, d_dense, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal launchers of libokinv (not part of the ABI).
+#pragma once
+
+#include "common.h"
+
+namespace okinv {
+
+enum Epilogue { EPI_NONE = 0, EPI_RV = 1, EPI_TS = 2 };
+
+// Deterministic block reduction of two complex values; thread 0 writes
+// partial[2*blockIdx.x] = sum d1, partial[2*blockIdx.x + 1] = sum d2.
+// Requires blockDim.x == 256 and that every thread of the block calls it.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sums d1, d2 over the block in a fixed order; the result is valid in thread 0.
+__device__ __forceinline__ void block_reduce2(double2& d1, double2& d2) {
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double a = wave_sum(d1.x), b = wave_sum(d1.y), c = wave_sum(d2.x), d = wave_sum(d2.y);
+    if (lane == 0) {
+        red[wave][0] = a;
+        red[wave][1] = b;
+        red[wave][2] = c;
+        red[wave][3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            s0 += red[w][0];
+            s1 += red[w][1];
+            s2 += red[w][2];
+            s3 += red[w][3];
+        }
+        d1 = make_double2(s0, s1);
+        d2 = make_double2(s2, s3);
+    }
+}
+
+__device__ __forceinline__ void block_reduce2_store(double2 d1, double2 d2, double2* partial) {
+    block_reduce2(d1, d2);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = d1;
+        partial[2 * blockIdx.x + 1] = d2;
+    }
+}
+
+// api.cpp
+int stencil_tps(int Wprec);
+
+// stencil.hip
+int apply_blocks(const Geo& g, int tps);
+int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int tps,
+                 int epi, const void* aux, double2* partial, hipStream_t st);
+
+// precompute.hip
+int launch_precompute(const Geo& g, const ok_coeffs& c, const double* links, int prec, void* W,
+                      void* scratch, hipStream_t st);
+int launch_to_dense(const Geo& g, const void* W, int prec, double* dense, hipStream_t st);
+
+// blas1.hip -- per right-hand side BiCGStab scalars live in device memory
+struct Scal {
+    double2 rho, rho_old, alpha, omega, beta, rv, ts;
+    double tt, rr, rr_true;
+    int flags;      // bit 0: breakdown seen (rho, <r^,v> or <t,t> vanished)
+    int pad;
+};
+
+int blas_blocks(const Geo& g);
+// fields of 12 V complex of type T (double or float)
+int launch_p_update(const Geo& g, bool f64, void* p, const void* r, const void* v, const Scal* sc, hipStream_t st);
+int launch_s_update(const Geo& g, bool f64, void* s, const void* r, const void* v, const Scal* sc, hipStream_t st);
+int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, const void* s, const void* t,
+                     const void* rhat, const Scal* sc, double2* partial, hipStream_t st);
+int launch_dot_rr(const Geo& g, bool f64, const void* rhat, const void* r, double2* partial, hipStream_t st);
+int launch_finish(int kind, int nblocks, const double2* partial, Scal* sc, hipStream_t st);
+enum Finish { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_RHO_REPLACE = 3, FIN_INIT = 4, FIN_TRUE = 5 };
+// r64 = xi - t64; optionally rlo = (float) r64; partial <r64, r64>
+int launch_residual(const Geo& g, const double* xi, const double* t64, double* r64, float* rlo,
+                    double2* partial, hipStream_t st);
+// x64 += (double) xlo; xlo = 0
+int launch_accum_x(const Geo& g, double* x64, float* xlo, hipStream_t st);
+int launch_copy(const Geo& g, bool f64, void* dst, const void* src, hipStream_t st);
+int launch_zero(const Geo& g, bool f64, void* dst, hipStream_t st);
+// partial <a, a> of an FP64 field (norm of the source)
+int launch_norm64(const Geo& g, const double* a, double2* partial, hipStream_t st);
+
+}  // namespace okinv

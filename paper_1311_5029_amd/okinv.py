@@ -1,0 +1,212 @@
+"""ctypes binding of libokinv (the C-ABI in include/okinv.h), same names as the C calls.
+
+Argument marshalling only: every step of the operator and the solver runs in
+the HIP library.  Device buffers are torch CUDA (HIP) tensors, passed by
+``data_ptr()``; the stream is torch's current stream unless given.  A negative
+status raises OkError with the library's message.  Importing this module fails
+loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libokinv.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libokinv.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+_lib = C.CDLL(LIB_PATH)
+
+OK_F64, OK_F32, OK_BF16 = 0, 1, 2
+OK_SUCCESS, OK_NOT_CONVERGED, OK_BREAKDOWN = 0, 1, 2
+OK_EINVAL, OK_ESIZE, OK_EALIGN, OK_EDEVICE, OK_ENONFINITE = -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "OK_SUCCESS", 1: "OK_NOT_CONVERGED", 2: "OK_BREAKDOWN", -1: "OK_EINVAL",
+                -2: "OK_ESIZE", -3: "OK_EALIGN", -4: "OK_EDEVICE", -5: "OK_ENONFINITE"}
+
+
+class ok_geom(C.Structure):
+    _fields_ = [("L", C.c_int32 * 4)]
+
+
+class ok_coeffs(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("mhat", "u0", "zeta", "r_s", "c_B", "c_E", "c_EE", "c_1", "c_2", "c_3", "c_4", "c_5")]
+
+
+class ok_solver_params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("delta", C.c_double), ("max_iter", C.c_int32),
+                ("max_restarts", C.c_int32), ("zero_guess", C.c_int32), ("verbose", C.c_int32)]
+
+
+class ok_solver_stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("matvec_hi", C.c_int32),
+                ("matvec_lo", C.c_int32), ("reliable_updates", C.c_int32), ("restarts", C.c_int32),
+                ("true_rel_resid", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_P = C.c_void_p
+_sig = {
+    "ok_abi_version": ([], C.c_int),
+    "ok_last_error": ([], C.c_char_p),
+    "ok_W_bytes": ([C.POINTER(ok_geom), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "ok_precompute_scratch_bytes": ([C.POINTER(ok_geom), C.POINTER(C.c_size_t)], C.c_int),
+    "ok_precompute_W": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), _P, C.c_int, _P, C.c_size_t, _P,
+                         C.c_size_t, _P], C.c_int),
+    "ok_apply_M": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), _P, C.c_int, _P, _P, C.c_int, C.c_int, _P],
+                   C.c_int),
+    "ok_W_to_dense": ([C.POINTER(ok_geom), _P, C.c_int, _P, _P], C.c_int),
+    "ok_bicgstab_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "ok_bicgstab": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, C.c_int,
+                     _P, _P, C.c_int, _P, C.c_size_t, C.POINTER(ok_solver_stats), _P], C.c_int),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_sig)
+
+
+class OkError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _check(rc):
+    if rc < 0:
+        raise OkError(rc, ok_last_error())
+    return rc
+
+
+def geom(dims):
+    g = ok_geom()
+    for i in range(4):
+        g.L[i] = int(dims[i])
+    return g
+
+
+def coeffs(c):
+    """ok_coeffs from any object with the attributes mhat, u0, zeta, ... (e.g. inputs.OKCoeffs)."""
+    out = ok_coeffs()
+    for n, _ in ok_coeffs._fields_:
+        setattr(out, n, float(getattr(c, n)))
+    return out
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def ok_abi_version():
+    return _lib.ok_abi_version()
+
+
+def ok_last_error():
+    return _lib.ok_last_error().decode()
+
+
+def ok_W_bytes(dims, prec):
+    n = C.c_size_t()
+    _check(_lib.ok_W_bytes(C.byref(geom(dims)), prec, C.byref(n)))
+    return n.value
+
+
+def ok_precompute_scratch_bytes(dims):
+    n = C.c_size_t()
+    _check(_lib.ok_precompute_scratch_bytes(C.byref(geom(dims)), C.byref(n)))
+    return n.value
+
+
+def ok_precompute_W(dims, c, d_links, prec, d_W, d_scratch, stream=None):
+    return _check(_lib.ok_precompute_W(C.byref(geom(dims)), C.byref(coeffs(c)), _ptr(d_links), prec,
+                                       _ptr(d_W), _nbytes(d_W), _ptr(d_scratch), _nbytes(d_scratch),
+                                       _stream(stream)))
+
+
+def ok_apply_M(dims, c, d_W, W_prec, d_psi, d_out, spinor_prec, nrhs=1, stream=None):
+    return _check(_lib.ok_apply_M(C.byref(geom(dims)), C.byref(coeffs(c)), _ptr(d_W), W_prec, _ptr(d_psi),
+                                  _ptr(d_out), spinor_prec, nrhs, _stream(stream)))
+
+
+def ok_W_to_dense(dims, d_W, prec, d_dense, stream=None):
+    return _check(_lib.ok_W_to_dense(C.byref(geom(dims)), _ptr(d_W), prec, _ptr(d_dense), _stream(stream)))
+
+
+def ok_bicgstab_workspace_bytes(dims, nrhs, Wlo_prec=-1):
+    n = C.c_size_t()
+    _check(_lib.ok_bicgstab_workspace_bytes(C.byref(geom(dims)), nrhs, Wlo_prec, C.byref(n)))
+    return n.value
+
+
+@dataclasses.dataclass
+class SolverParams:
+    tol: float = 1e-10
+    delta: float = 0.1
+    max_iter: int = 10000
+    max_restarts: int = 5
+    zero_guess: int = 1
+    verbose: int = 0
+
+    def c(self):
+        return ok_solver_params(self.tol, self.delta, self.max_iter, self.max_restarts,
+                                self.zero_guess, self.verbose)
+
+
+def ok_bicgstab(dims, c, params, d_W64, d_Wlo, Wlo_prec, d_xi, d_psi, nrhs, d_work, stream=None):
+    """Returns (status, [stats dict per right-hand side])."""
+    stats = (ok_solver_stats * nrhs)()
+    p = params.c() if isinstance(params, SolverParams) else params
+    rc = _lib.ok_bicgstab(C.byref(geom(dims)), C.byref(coeffs(c)), C.byref(p), _ptr(d_W64), _ptr(d_Wlo),
+                          Wlo_prec, _ptr(d_xi), _ptr(d_psi), nrhs, _ptr(d_work), _nbytes(d_work), stats,
+                          _stream(stream))
+    _check(rc)
+    return rc, [s.as_dict() for s in stats]
+
+
+# --------------------------------------------------------------------------- plumbing
+def to_device_complex(a, dtype="float64", device="cuda"):
+    """NumPy complex array -> contiguous torch tensor of interleaved (re, im) reals on the device."""
+    import torch
+    a = np.ascontiguousarray(a)
+    real = np.ascontiguousarray(a.view(np.float64) if a.dtype == np.complex128
+                                else a.astype(np.complex128).view(np.float64))
+    t = torch.from_numpy(real)
+    if dtype == "float32":
+        t = t.to(torch.float32)
+    return t.to(device)
+
+
+def to_host_complex(t, shape=None):
+    """torch tensor of interleaved (re, im) -> NumPy complex128 (optionally reshaped)."""
+    a = t.detach().to("cpu").double().numpy()
+    z = a.reshape(-1, 2)
+    out = z[:, 0] + 1j * z[:, 1]
+    return out.reshape(shape) if shape is not None else out
+
+
+def empty_bytes(n, device="cuda"):
+    """A device buffer of n bytes (256-byte granularity), as a uint8 tensor."""
+    import torch
+    return torch.empty(max(256, (n + 255) // 256 * 256), dtype=torch.uint8, device=device)

@@ -1,0 +1,75 @@
+"""Device plumbing for the GPU tests: uploads, W precompute and M applications
+through the C-ABI binding (torch only allocates memory and provides the stream)."""
+import numpy as np
+
+from paper_1311_5029_amd import inputs as I
+
+
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU visible")
+    from paper_1311_5029_amd import okinv   # raises if libokinv.so is missing
+    return okinv
+
+
+class Lattice:
+    """Links uploaded once; W precomputed per precision on demand."""
+
+    def __init__(self, dims, U, c):
+        import torch
+        self.ok = lib()
+        self.torch = torch
+        self.dims = tuple(dims)
+        self.V = int(np.prod(dims))
+        self.U = U
+        self.c = c
+        self.links = self.ok.to_device_complex(U)
+        self.W = {}
+
+    def precompute(self, prec):
+        ok = self.ok
+        if prec not in self.W:
+            W = ok.empty_bytes(ok.ok_W_bytes(self.dims, prec))
+            scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(self.dims))
+            ok.ok_precompute_W(self.dims, self.c, self.links, prec, W, scr)
+            self.torch.cuda.synchronize()
+            del scr
+            self.W[prec] = W
+        return self.W[prec]
+
+    def dense_W(self, prec):
+        """GPU W expanded to FP64, as (Lt, Lz, Ly, Lx, 27, 12, 12) complex."""
+        ok = self.ok
+        d = self.torch.empty(self.V * 27 * 144 * 2, dtype=self.torch.float64, device="cuda")
+        ok.ok_W_to_dense(self.dims, self.precompute(prec), prec, d)
+        self.torch.cuda.synchronize()
+        return ok.to_host_complex(d, I.lattice_shape(self.dims) + (27, 12, 12))
+
+    def spinor_dtype(self, prec):
+        return "float64" if prec == self.ok.OK_F64 else "float32"
+
+    def apply_dev(self, prec, psi_dev, nrhs=1, c=None):
+        ok = self.ok
+        out = self.torch.empty_like(psi_dev)
+        sp = ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32
+        ok.ok_apply_M(self.dims, c or self.c, self.precompute(prec), prec, psi_dev, out, sp, nrhs)
+        return out
+
+    def apply(self, prec, psi, c=None):
+        """M psi for a host spinor psi (..., Lt, Lz, Ly, Lx, 4, 3); returns complex128."""
+        ok = self.ok
+        nrhs = int(np.prod(psi.shape[:-6])) if psi.ndim > 6 else 1
+        d = ok.to_device_complex(psi, dtype=self.spinor_dtype(prec))
+        out = self.apply_dev(prec, d, nrhs, c)
+        self.torch.cuda.synchronize()
+        return ok.to_host_complex(out, psi.shape)
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def maxrel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))

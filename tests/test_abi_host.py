@@ -1,0 +1,150 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared symbol,
+and rejects bad arguments before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1311_5029_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "okinv.h")
+LIB = os.path.join(ROOT, "paper_1311_5029_amd", "libokinv.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libokinv.so not built")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(ok_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_1311_5029_amd import okinv
+    assert sorted(okinv.EXPORTED) == declared_functions()
+
+
+def test_abi_version():
+    from paper_1311_5029_amd import okinv
+    assert okinv.ok_abi_version() == 1
+
+
+def test_size_queries():
+    from paper_1311_5029_amd import okinv
+    dims = (20, 20, 20, 64)
+    V = 20 ** 3 * 64
+    assert okinv.ok_W_bytes(dims, okinv.OK_F32) == 27 * 144 * 8 * V
+    assert okinv.ok_W_bytes(dims, okinv.OK_F64) == 27 * 144 * 16 * V
+    assert okinv.ok_W_bytes(dims, okinv.OK_BF16) == 27 * 144 * 4 * V
+    # site stride padded to a multiple of 64
+    assert okinv.ok_W_bytes((5, 5, 5, 5), okinv.OK_F32) == 27 * 144 * 8 * 640
+    assert okinv.ok_precompute_scratch_bytes((4, 4, 4, 4)) == 6 * 9 * 16 * 256
+    assert okinv.ok_bicgstab_workspace_bytes((4, 4, 4, 4), 1) >= 6 * 256 * 192
+    assert okinv.ok_bicgstab_workspace_bytes((4, 4, 4, 4), 1, okinv.OK_F32) >= 7 * 256 * 96
+
+
+@pytest.mark.parametrize("dims", [(2, 4, 4, 4), (4, 4, 4, 0), (4, 4, -1, 4), (5000, 4, 4, 4)])
+def test_bad_geometry_rejected(dims):
+    from paper_1311_5029_amd import okinv
+    with pytest.raises(okinv.OkError) as e:
+        okinv.ok_W_bytes(dims, okinv.OK_F32)
+    assert e.value.status == okinv.OK_EINVAL
+    assert "L[" in okinv.ok_last_error()
+
+
+def test_bad_precision_rejected():
+    from paper_1311_5029_amd import okinv
+    with pytest.raises(okinv.OkError) as e:
+        okinv.ok_W_bytes((4, 4, 4, 4), 7)
+    assert e.value.status == okinv.OK_EINVAL
+
+
+def test_apply_validation_before_device():
+    from paper_1311_5029_amd import okinv
+    c = I.standin_coeffs()
+    g = okinv.geom((4, 4, 4, 4))
+    cc = okinv.coeffs(c)
+    lib = okinv._lib
+    # null pointers
+    rc = lib.ok_apply_M(ctypes.byref(g), ctypes.byref(cc), None, okinv.OK_F32, None, None, okinv.OK_F32, 1, None)
+    assert rc == okinv.OK_EINVAL
+    # misaligned pointers
+    rc = lib.ok_apply_M(ctypes.byref(g), ctypes.byref(cc), 0x1001, okinv.OK_F32, 0x2000, 0x900000, okinv.OK_F32, 1, None)
+    assert rc == okinv.OK_EALIGN
+    # unsupported precision pair (FP64 W with FP32 spinors)
+    rc = lib.ok_apply_M(ctypes.byref(g), ctypes.byref(cc), 0x1000, okinv.OK_F64, 0x2000, 0x900000, okinv.OK_F32, 1, None)
+    assert rc == okinv.OK_EINVAL
+    # aliasing in and out
+    rc = lib.ok_apply_M(ctypes.byref(g), ctypes.byref(cc), 0x1000, okinv.OK_F32, 0x2000, 0x2100, okinv.OK_F32, 1, None)
+    assert rc == okinv.OK_EINVAL and "overlap" in okinv.ok_last_error()
+    # nrhs out of range
+    rc = lib.ok_apply_M(ctypes.byref(g), ctypes.byref(cc), 0x1000, okinv.OK_F32, 0x2000, 0x900000, okinv.OK_F32, 0, None)
+    assert rc == okinv.OK_EINVAL
+    # non-finite coefficient
+    cc.c_3 = float("nan")
+    rc = lib.ok_apply_M(ctypes.byref(g), ctypes.byref(cc), 0x1000, okinv.OK_F32, 0x2000, 0x900000, okinv.OK_F32, 1, None)
+    assert rc == okinv.OK_EINVAL
+
+
+def test_precompute_validation_before_device():
+    from paper_1311_5029_amd import okinv
+    c = okinv.coeffs(I.standin_coeffs())
+    g = okinv.geom((4, 4, 4, 4))
+    lib = okinv._lib
+    need = okinv.ok_W_bytes((4, 4, 4, 4), okinv.OK_F32)
+    scr = okinv.ok_precompute_scratch_bytes((4, 4, 4, 4))
+    # W too small
+    rc = lib.ok_precompute_W(ctypes.byref(g), ctypes.byref(c), 0x10000000, okinv.OK_F32, 0x20000000, need - 16,
+                             0x40000000, scr, None)
+    assert rc == okinv.OK_ESIZE
+    # scratch too small
+    rc = lib.ok_precompute_W(ctypes.byref(g), ctypes.byref(c), 0x10000000, okinv.OK_F32, 0x20000000, need,
+                             0x40000000, scr - 1, None)
+    assert rc == okinv.OK_ESIZE
+    # u0 <= 0
+    c.u0 = 0.0
+    rc = lib.ok_precompute_W(ctypes.byref(g), ctypes.byref(c), 0x10000000, okinv.OK_F32, 0x20000000, need,
+                             0x40000000, scr, None)
+    assert rc == okinv.OK_EINVAL
+
+
+def test_solver_validation_before_device():
+    from paper_1311_5029_amd import okinv
+    dims = (4, 4, 4, 4)
+    c = okinv.coeffs(I.standin_coeffs())
+    g = okinv.geom(dims)
+    lib = okinv._lib
+    stats = (okinv.ok_solver_stats * 1)()
+    need = okinv.ok_bicgstab_workspace_bytes(dims, 1)
+    good = okinv.SolverParams().c()
+    args = lambda p, work, wlo=None, wlo_prec=-1: (
+        ctypes.byref(g), ctypes.byref(c), ctypes.byref(p), 0x10000000, wlo, wlo_prec, 0x20000000, 0x30000000, 1,
+        0x40000000, work, stats, None)
+    assert lib.ok_bicgstab(*args(good, need - 256)) == okinv.OK_ESIZE
+    bad = okinv.SolverParams(tol=-1.0).c()
+    assert lib.ok_bicgstab(*args(bad, need)) == okinv.OK_EINVAL
+    bad = okinv.SolverParams(delta=1.5).c()
+    assert lib.ok_bicgstab(*args(bad, need)) == okinv.OK_EINVAL
+    # low-precision W given with an FP64 precision tag
+    need2 = okinv.ok_bicgstab_workspace_bytes(dims, 1, okinv.OK_F32)
+    assert lib.ok_bicgstab(*args(good, need2, 0x50000000, okinv.OK_F64)) == okinv.OK_EINVAL
+
+
+def test_host_complex_roundtrip():
+    torch = pytest.importorskip("torch")
+    from paper_1311_5029_amd import okinv
+    a = I.gaussian_sources((3, 3, 3, 3), 1, 1)[0]
+    t = okinv.to_device_complex(a, device="cpu")
+    assert t.dtype == torch.float64 and t.numel() == a.size * 2
+    assert np.array_equal(okinv.to_host_complex(t, a.shape), a)

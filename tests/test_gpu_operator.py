@@ -1,0 +1,183 @@
+"""GPU parity of ok_precompute_W and ok_apply_M against the FP64 oracle.
+
+Tolerances:
+  * W, FP64 storage: max |dW| <= 1e-13 max |W| (FP64 arithmetic, different order);
+  * W, FP32 storage: every entry the correctly rounded FP32 of the FP64 value,
+    |dW| <= 2^-24 |W| (+1e-15 max|W| for the FP64 evaluation-order noise);
+  * W, BF16 storage: |dW| <= 2^-8 |W| (round-to-nearest via FP32);
+  * M psi: 1e-12 relative in FP64, 1e-6 in FP32 (FP32 W and psi, FP32
+    accumulation of 324 products per component), and 1e-2 with BF16 W (relative
+    rounding 2^-9 per W entry, random signs over 324 terms).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.local import apply_at_sites
+from oracle.route_a import WForm
+from oracle.route_b import OKOperatorB
+from paper_1311_5029_amd import inputs as I
+
+from gpu_util import Lattice, lib, maxrel, rel
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(4, 4, 4, 4), (5, 6, 7, 3), (6, 5, 4, 7), (8, 6, 10, 4)]
+TOL_APPLY = {0: 1e-12, 1: 1e-6, 2: 1e-2}
+
+
+def make(dims, eps=0.45, seed=11, u0=None):
+    U = I.random_su3_links(dims, eps, seed)
+    c = I.standin_coeffs(m0=0.5, u0=u0 if u0 is not None else I.tadpole_u0(U))
+    return U, c
+
+
+@pytest.fixture(scope="module", params=DIMS, ids=lambda d: "x".join(map(str, d)))
+def lat(request):
+    dims = request.param
+    U, c = make(dims)
+    L = Lattice(dims, U, c)
+    L.oracle_W = WForm(U, c).W
+    L.oracle_B = OKOperatorB(U, c)
+    return L
+
+
+def test_precompute_f64_blockwise(lat):
+    ok = lib()
+    got = lat.dense_W(ok.OK_F64)
+    ref = lat.oracle_W
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_precompute_f32_correctly_rounded(lat):
+    ok = lib()
+    got = lat.dense_W(ok.OK_F32)
+    ref = lat.oracle_W
+    m = np.max(np.abs(ref))
+    for part in (np.real, np.imag):
+        d = np.abs(part(got) - part(ref))
+        assert np.all(d <= 2.0 ** -24 * np.abs(part(ref)) + 1e-15 * m)
+
+
+def test_precompute_bf16_rounding(lat):
+    ok = lib()
+    got = lat.dense_W(ok.OK_BF16)
+    ref = lat.oracle_W
+    m = np.max(np.abs(ref))
+    for part in (np.real, np.imag):
+        d = np.abs(part(got) - part(ref))
+        assert np.all(d <= 2.0 ** -8 * np.abs(part(ref)) + 1e-15 * m)
+
+
+def test_backward_blocks_exact_gamma5_partners(lat):
+    """Backward blocks are bit-exact gamma5 conjugates of the stored forward blocks."""
+    ok = lib()
+    from oracle.basis import gamma5_conj
+    from oracle.lattice import shift_vec
+    from oracle.route_a import FWD_OF_BWD, offsets
+    offs = offsets()
+    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
+        W = lat.dense_W(prec)
+        for kb, kf in FWD_OF_BWD.items():
+            src = shift_vec(W[..., kf, :, :], [-v for v in offs[kf]])
+            assert np.array_equal(W[..., kb, :, :], gamma5_conj(src))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "bf16"])
+@pytest.mark.parametrize("tps", [1, 2, 4])
+def test_apply_matches_oracle(lat, prec, tps, monkeypatch):
+    monkeypatch.setenv("OKINV_TPS", str(tps))
+    psi = I.gaussian_sources(lat.dims, 1, 21)[0]
+    ref = lat.oracle_B.apply(psi)
+    got = lat.apply(prec, psi)
+    tol = TOL_APPLY[prec]
+    assert rel(got, ref) <= tol
+    assert maxrel(got, ref) <= tol * (1.0 if prec == 0 else 3.0)
+
+
+def test_apply_multiple_rhs(lat):
+    ok = lib()
+    psi = I.gaussian_sources(lat.dims, 3, 22)
+    got = lat.apply(ok.OK_F64, psi)
+    for k in range(3):
+        assert np.array_equal(got[k], lat.apply(ok.OK_F64, psi[k]))
+
+
+def test_apply_mass_change_needs_no_precompute(lat):
+    ok = lib()
+    psi = I.gaussian_sources(lat.dims, 1, 23)[0]
+    c2 = I.OKCoeffs(**{**lat.c.__dict__, "mhat": lat.c.mhat + 0.7})
+    a = lat.apply(ok.OK_F64, psi)
+    b = lat.apply(ok.OK_F64, psi, c=c2)
+    assert rel(b - a, 0.7 * psi) < 1e-13
+
+
+def test_apply_deterministic(lat):
+    ok = lib()
+    psi = I.gaussian_sources(lat.dims, 1, 24)[0]
+    for prec in (ok.OK_F64, ok.OK_F32):
+        assert np.array_equal(lat.apply(prec, psi), lat.apply(prec, psi))
+
+
+def test_apply_l3_coinciding_offsets():
+    """L = 3: x + 2i coincides with x - i, the contributions add."""
+    ok = lib()
+    dims = (3, 4, 3, 5)
+    U, c = make(dims, seed=5)
+    L = Lattice(dims, U, c)
+    psi = I.gaussian_sources(dims, 1, 25)[0]
+    assert rel(L.apply(ok.OK_F64, psi), OKOperatorB(U, c).apply(psi)) < 1e-12
+
+
+def test_free_field_plane_wave_f64():
+    ok = lib()
+    from oracle.free import symbol_matrix
+    dims = (6, 4, 5, 8)
+    c = I.standin_coeffs(u0=0.93)
+    L = Lattice(dims, I.unit_links(dims), c)
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx), indexing="ij")
+    n = (2, 1, 3, 5)
+    k = [2 * np.pi * n[m] / dims[m] for m in range(4)]
+    ph = np.exp(1j * (k[0] * x + k[1] * y + k[2] * z + k[3] * t))
+    chi = np.arange(12).reshape(4, 3) + 1j
+    got = L.apply(ok.OK_F64, ph[..., None, None] * chi)
+    want = ph[..., None, None] * (symbol_matrix(k, c) @ chi)
+    assert rel(got, want) < 1e-13
+
+
+# --- full size: 20^3 x 64, plaquette ~ 0.6 ------------------------------------------
+@pytest.fixture(scope="module")
+def big():
+    ok = lib()
+    dims = (20, 20, 20, 64)
+    cfg = I.make_config("C3")
+    L = Lattice(dims, cfg["U"], cfg["coeffs"])
+    L.precompute(ok.OK_F32)
+    L.precompute(ok.OK_F64)
+    return L
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "bf16"])
+def test_full_size_sampled_sites(big, prec):
+    """Sampled sites of M psi at 20^3 x 64 against the oracle evaluated site by site."""
+    psi = I.gaussian_sources(big.dims, 1, 31)[0]
+    got = big.apply(prec, psi)
+    rng = np.random.default_rng(7)
+    sites = [(0, 0, 0, 0), (19, 19, 19, 63)] + [tuple(int(v) for v in rng.integers(0, [20, 20, 20, 64]))
+                                                for _ in range(6)]
+    ref = apply_at_sites(big.U, psi, big.c, sites)
+    gs = np.stack([got[t, z, y, x] for (x, y, z, t) in sites])
+    assert rel(gs, ref) <= TOL_APPLY[prec]
+
+
+def test_full_size_gamma5_hermiticity(big):
+    """<phi, g5 M g5 psi> = <M phi, psi> with the GPU operator at 20^3 x 64 (FP64)."""
+    ok = lib()
+    from oracle.basis import GAMMA5
+    phi, psi = I.gaussian_sources(big.dims, 2, 32)
+    g5 = lambda f: GAMMA5 @ f
+    a = np.vdot(phi, g5(big.apply(ok.OK_F64, g5(psi))))
+    b = np.vdot(big.apply(ok.OK_F64, phi), psi)
+    assert abs(a - b) / abs(b) < 1e-12

@@ -1,0 +1,159 @@
+"""GPU BiCGStab (ok_bicgstab) judged by the FP64 oracle.
+
+Several solutions are correct (any psi with small enough residual), so the judge
+is the true residual ||xi - M psi|| / ||xi|| computed with the oracle's M; psi is
+compared directly only where an exact solution exists (dense LU on 4^4, the FFT
+point-source solution of a pure-gauge field), within kappa(M) times the tolerance.
+"""
+import numpy as np
+import pytest
+
+from oracle.dense import dense_from_W
+from oracle.free import pure_gauge_point_solution
+from oracle.route_a import WForm, offsets
+from oracle.route_b import OKOperatorB
+from paper_1311_5029_amd import inputs as I
+
+from gpu_util import Lattice, lib
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+# the library checks its own FP64 residual; the oracle's M differs by rounding only
+ORACLE_SLACK = 1.05
+
+
+def solve(L, xi, low=None, params=None, guess=None):
+    ok = L.ok
+    torch = L.torch
+    nrhs = xi.shape[0] if xi.ndim == 7 else 1
+    d_xi = ok.to_device_complex(xi)
+    psi = ok.to_device_complex(guess) if guess is not None else torch.zeros_like(d_xi)
+    lo_prec = -1 if low is None else low
+    work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(L.dims, nrhs, lo_prec))
+    W64 = L.precompute(ok.OK_F64)
+    Wlo = None if low is None else L.precompute(low)
+    p = params or ok.SolverParams(tol=TOL)
+    if guess is not None:
+        p.zero_guess = 0
+    rc, st = ok.ok_bicgstab(L.dims, L.c, p, W64, Wlo, lo_prec, d_xi, psi, nrhs, work)
+    torch.cuda.synchronize()
+    return rc, st, ok.to_host_complex(psi, xi.shape)
+
+
+def oracle_resid(U, c, xi, x):
+    op = OKOperatorB(U, c)
+    return np.linalg.norm((xi - op.apply(x)).ravel()) / np.linalg.norm(xi.ravel())
+
+
+@pytest.fixture(scope="module")
+def c1():
+    dims = (4, 4, 4, 4)
+    U = I.random_su3_links(dims, 0.3, I.SEED_LINKS + 1)
+    c = I.standin_coeffs(m0=0.5, u0=I.tadpole_u0(U))
+    xi = I.gaussian_sources(dims, 1, I.SEED_SOURCES + 1)[0]
+    L = Lattice(dims, U, c)
+    M = dense_from_W(WForm(U, c).W, c.mhat, dims, offsets())
+    sv = np.linalg.svd(M, compute_uv=False)
+    L.kappa = sv[0] / sv[-1]
+    L.x_lu = np.linalg.solve(M, xi.ravel()).reshape(xi.shape)
+    L.xi = xi
+    return L
+
+
+def test_c1_plain_matches_dense_lu(c1):
+    ok = lib()
+    rc, st, x = solve(c1, c1.xi)
+    assert rc == ok.OK_SUCCESS and st[0]["status"] == 0
+    assert st[0]["true_rel_resid"] <= TOL
+    assert oracle_resid(c1.U, c1.c, c1.xi, x) <= ORACLE_SLACK * TOL
+    err = np.linalg.norm(x - c1.x_lu) / np.linalg.norm(c1.x_lu)
+    assert err <= c1.kappa * TOL
+
+
+@pytest.mark.parametrize("low", [1, 2], ids=["f32", "bf16"])
+def test_c1_mixed_precision(c1, low):
+    ok = lib()
+    rc, st, x = solve(c1, c1.xi, low=low)
+    assert rc == ok.OK_SUCCESS
+    assert st[0]["reliable_updates"] >= 1 and st[0]["matvec_lo"] > 0
+    assert oracle_resid(c1.U, c1.c, c1.xi, x) <= ORACLE_SLACK * TOL
+    err = np.linalg.norm(x - c1.x_lu) / np.linalg.norm(c1.x_lu)
+    assert err <= c1.kappa * TOL
+
+
+def test_zero_source_gives_zero(c1):
+    ok = lib()
+    rc, st, x = solve(c1, np.zeros_like(c1.xi))
+    assert rc == ok.OK_SUCCESS and st[0]["iterations"] == 0 and np.all(x == 0)
+
+
+def test_nonfinite_source_rejected(c1):
+    ok = lib()
+    xi = c1.xi.copy()
+    xi[1, 2, 3, 0, 2, 1] = np.nan
+    with pytest.raises(ok.OkError) as e:
+        solve(c1, xi)
+    assert e.value.status == ok.OK_ENONFINITE
+
+
+def test_max_iter_reports_not_converged(c1):
+    ok = lib()
+    rc, st, x = solve(c1, c1.xi, params=ok.SolverParams(tol=TOL, max_iter=1))
+    assert rc == ok.OK_NOT_CONVERGED and st[0]["status"] == ok.OK_NOT_CONVERGED
+    assert st[0]["iterations"] == 1 and st[0]["true_rel_resid"] > TOL
+
+
+def test_guess_is_used(c1):
+    ok = lib()
+    rc, st, x = solve(c1, c1.xi, guess=c1.x_lu)
+    assert rc == ok.OK_SUCCESS and st[0]["iterations"] <= 1
+
+
+def test_solve_deterministic(c1):
+    _, _, a = solve(c1, c1.xi)
+    _, _, b = solve(c1, c1.xi)
+    assert np.array_equal(a, b)
+
+
+def test_multiple_rhs_and_ragged_lattice():
+    ok = lib()
+    dims = (5, 6, 7, 4)
+    U = I.random_su3_links(dims, 0.3, 17)
+    c = I.standin_coeffs(m0=0.5, u0=I.tadpole_u0(U))
+    L = Lattice(dims, U, c)
+    xi = I.gaussian_sources(dims, 3, 18)
+    for low in (None, ok.OK_F32):
+        rc, st, x = solve(L, xi, low=low)
+        assert rc == ok.OK_SUCCESS and len(st) == 3
+        for k in range(3):
+            assert oracle_resid(U, c, xi[k], x[k]) <= ORACLE_SLACK * TOL
+
+
+def test_plaquette06_mixed_vs_plain():
+    """8^3 x 16 at plaquette ~ 0.6 (the C2 link ensemble at a smaller volume)."""
+    ok = lib()
+    dims = (8, 8, 8, 16)
+    cfg = I.make_config("C2", dims=dims)
+    L = Lattice(dims, cfg["U"], cfg["coeffs"])
+    xi = cfg["xi"][0]
+    rc64, st64, x64 = solve(L, xi)
+    rc32, st32, x32 = solve(L, xi, low=ok.OK_F32)
+    assert rc64 == rc32 == ok.OK_SUCCESS
+    for x in (x64, x32):
+        assert oracle_resid(cfg["U"], cfg["coeffs"], xi, x) <= ORACLE_SLACK * TOL
+
+
+def test_pure_gauge_point_sources_fft():
+    """12 point sources on a pure-gauge 8^3 x 12 field against the exact FFT solution."""
+    ok = lib()
+    dims = (8, 8, 8, 12)
+    U, g = I.pure_gauge_links(dims, 51)
+    c = I.standin_coeffs(m0=0.5, u0=1.0)
+    L = Lattice(dims, U, c)
+    xi = I.point_sources(dims)
+    rc, st, x = solve(L, xi, low=ok.OK_F32)
+    assert rc == ok.OK_SUCCESS
+    exact = pure_gauge_point_solution(dims, c, g, xi[:, 0, 0, 0, 0])
+    for k in range(12):
+        assert np.linalg.norm(x[k] - exact[k]) / np.linalg.norm(exact[k]) < 1e-8

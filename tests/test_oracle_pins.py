@@ -464,3 +464,17 @@ def test_planted_clockwise_leaf_is_caught(monkeypatch):
         return good_leaves(U, mu, nu) - first + dag(first)     # first leaf run clockwise
     monkeypatch.setattr(cl, "clover_leaves", bad_leaves)
     assert _abelian_clover_error(cl.field_strength) > 1e-3
+
+
+# --- local evaluation used for sampled parity at full lattice size ----------------
+def test_local_window_evaluation_matches_global():
+    from oracle.local import apply_at_sites
+    dims = (10, 9, 11, 6)
+    U = I.random_su3_links(dims, 0.45, 41)
+    c = all_on(u0=0.88)
+    psi = I.gaussian_sources(dims, 1, 42)[0]
+    full = OKOperatorB(U, c).apply(psi)
+    sites = [(0, 0, 0, 0), (9, 8, 10, 5), (4, 2, 7, 3), (1, 8, 0, 5)]
+    loc = apply_at_sites(U, psi, c, sites)
+    for n, (x, y, z, t) in enumerate(sites):
+        assert np.max(np.abs(loc[n] - full[t, z, y, x])) < 1e-13 * np.max(np.abs(full))
