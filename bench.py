@@ -1,0 +1,361 @@
+"""Benchmark of the OK-operator hot path on one MI355X.
+
+Workload: 20^3 x 64 lattice (512,000 sites), random SU(3) links U = exp(i eps H)
+with eps tuned to an average plaquette of 0.6, tadpole u0 from the plaquette,
+the stand-in coefficient set at m0 a = 0.5, and the 12 spin-colour point
+sources at the origin.
+
+One step = one application of M (ok_apply_M) to the 12-right-hand-side batch,
+with the chosen storage of W (FP32 by default).  The metric is the HBM
+throughput of that application in algorithmic bytes (dense W streamed once per
+right-hand side applied + one spinor read and one written, per site), timed
+with HIP events on the stream the library launches on.  The second half of the
+metric, time to ||xi - M psi||/||xi|| <= 1e-10, is measured on the same batch:
+"plain" = FP64 BiCGStab, one right-hand side after the other; "chosen" =
+BiCGStab in FP32 fields with BF16 W and FP64 reliable updates.
+
+Prints one JSON line.  --gpus N > 1 is refused (single-GPU build).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (20, 20, 20, 64)
+V = 20 * 20 * 20 * 64
+NRHS = 12
+# algorithmic bytes per site of one single-right-hand-side application: dense
+# 27 x 12x12 complex W + spinor in + spinor out
+BYTES_SITE = {0: 27 * 144 * 16 + 2 * 192, 1: 27 * 144 * 8 + 2 * 96, 2: 27 * 144 * 4 + 2 * 96}
+PREC_NAME = {0: "f64", 1: "f32", 2: "bf16"}
+KERNEL_NAME = "k_apply"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("stencil.hip", "wlayout.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1311_5029_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(form):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 PMC
+    summary, or None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_apply_%s_20x20x20x64_traffic.json" % form)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_sha") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+COPY_BYTES = 1 << 30
+
+
+def is_apply_kernel(name, form):
+    """Whether a (mangled or demangled) kernel name is the single-RHS apply of this form
+    without a reduction epilogue: k_apply<prec, threads-per-site, 0>."""
+    p = {"f64": 0, "f32": 1, "bf16": 2}[form]
+    return any(("k_apply<%d, %d, 0>" % (p, t)) in name or ("k_applyILi%dELi%dELi0E" % (p, t)) in name
+               for t in (1, 2, 4))
+
+
+def copy_probe():
+    """A plain 1 GiB device-to-device copy (one kernel of known traffic) used to
+    calibrate the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def _read_counters(d):
+    """{(kernel, dispatch): {counter: value}} from the counter_collection CSVs under d."""
+    import csv
+    out = {}
+    for dirpath, _, files in os.walk(d):
+        for f in files:
+            if not f.endswith("counter_collection.csv"):
+                continue
+            with open(os.path.join(dirpath, f)) as fh:
+                for row in csv.DictReader(fh):
+                    key = (row.get("Kernel_Name", ""), row.get("Dispatch_Id", row.get("Correlation_Id", "")))
+                    cn = row.get("Counter_Name")
+                    out.setdefault(key, {})
+                    out[key][cn] = out[key].get(cn, 0.0) + float(row.get("Counter_Value", 0.0))
+    return out
+
+
+def parse_pmc(fetch_dir, write_dir, form):
+    """Average FETCH_SIZE + WRITE_SIZE (KiB per dispatch) of the dominant kernel,
+    each scaled by the same counter's reading for the 1 GiB copy; writes the
+    traffic summary consumed by the benchmark's roofline entry."""
+    res = {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _read_counters(d)
+        ker = [v[cname] for (k, _), v in rows.items() if cname in v and is_apply_kernel(k, form)]
+        cop = [v[cname] for (k, _), v in rows.items() if "copy" in k.lower() and cname in v]
+        cop = [x for x in cop if x * 1024 > 0.5 * COPY_BYTES]
+        if not ker or not cop:
+            raise SystemExit("no %s samples for the kernel or the copy in %s" % (cname, d))
+        scale = COPY_BYTES / (1024.0 * float(np.median(cop)))
+        res[cname] = {"kib_per_dispatch": float(np.mean(ker)), "dispatches": len(ker),
+                      "copy_kib": float(np.median(cop)), "scale": scale,
+                      "bytes_per_launch": float(np.mean(ker)) * 1024.0 * scale}
+    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    prec = {"f64": 0, "f32": 1, "bf16": 2}[form]
+    out = {"kernel": "%s<%s> (single RHS, no epilogue)" % (KERNEL_NAME, form), "lattice": list(DIMS),
+           "bytes_per_launch": total, "algorithmic_bytes_per_launch": BYTES_SITE[prec] * V,
+           "ratio_to_algorithmic": total / (BYTES_SITE[prec] * V), "counters": res,
+           "source_sha": source_hash()}
+    path = os.path.join(ROOT, "profiles", "k_apply_%s_20x20x20x64_traffic.json" % form)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def summarize_trace(d, out_path, command):
+    """Short text summary of a rocprofv3 --kernel-trace --stats run (top kernels by time)."""
+    import csv
+    import re
+    files = [os.path.join(dp, f) for dp, _, fs in os.walk(d) for f in fs if f.endswith("kernel_stats.csv")]
+    rows = list(csv.DictReader(open(files[0])))
+    lines = ["# rocprofv3 kernel statistics", "", "command: " + command, "",
+             "%-44s %6s %14s %8s" % ("kernel", "calls", "avg ns", "% time")]
+    for r in rows[:14]:
+        name = r["Name"].replace("okinv::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+        name = re.sub(r"\(.*", "", name).replace("void ", "")[:44]
+        lines.append("%-44s %6s %14.0f %8.2f" % (name, r["Calls"], float(r["AverageNs"]), float(r["Percentage"])))
+    for form, prec in (("f64", 0), ("f32", 1), ("bf16", 2)):
+        for r in rows:
+            if is_apply_kernel(r["Name"], form):
+                ns = float(r["AverageNs"])
+                gbs = BYTES_SITE[prec] * V / ns
+                lines.append("")
+                lines.append("%s: %s average %.0f ns per launch -> %.1f GB/s algorithmic (%d B/site x %d sites), "
+                             "%.1f%% of 8 TB/s" % (form, re.sub(r"\(.*", "", r["Name"].split("::")[-1]), ns, gbs,
+                                                   BYTES_SITE[prec], V, gbs / HBM_PEAK_GBS * 100))
+                break
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def cpu_baseline():
+    """The FP64 oracle (operator composition from the links) on a bounded sample:
+    the full 20^3 spatial volume over 32 of the 64 time slices, one application,
+    one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.route_b import OKOperatorB
+    from paper_1311_5029_amd import inputs as I
+    dims = (20, 20, 20, 32)
+    U = I.random_su3_links(dims, I.config_epsilon("plaq0.6"), I.SEED_LINKS + 3)
+    c = I.standin_coeffs(m0=0.5, u0=I.tadpole_u0(U))
+    psi = I.gaussian_sources(dims, 1, I.SEED_SOURCES + 3)[0]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        op = OKOperatorB(U, c)
+        t1 = time.perf_counter()
+        op.apply(psi)
+        t2 = time.perf_counter()
+    sites = int(np.prod(dims))
+    sps = sites / (t2 - t1)
+    return {
+        "value": round(sps * BYTES_SITE[1] / 1e9, 4),
+        "unit": "GB/s (FP32 W-form algorithmic bytes equivalent)",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "one M.psi at 20^3x32 (half the 20^3x64 workload), route-B FP64 NumPy, "
+                  "%.1f s apply + %.1f s link setup; %.0f sites/s" % (t2 - t1, t1 - t0, sps),
+        "sites_per_s": round(sps, 1),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
+    ap.add_argument("--parse-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs into the traffic file and exit")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"),
+                    help="write a text summary of a rocprofv3 --kernel-trace --stats run and exit")
+    args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.parse_pmc:
+        parse_pmc(args.parse_pmc[0], args.parse_pmc[1], args.form)
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d refused)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1311_5029_amd import inputs as I
+    from paper_1311_5029_amd import okinv as ok
+
+    torch.cuda.set_device(0)
+    form = {"f64": ok.OK_F64, "f32": ok.OK_F32, "bf16": ok.OK_BF16}[args.form]
+    log("generating links 20^3x64")
+    t0 = time.time()
+    cfg = I.make_config("C3")
+    c = cfg["coeffs"]
+    log("links in %.1fs, plaquette^(1/4) = u0 = %.5f, eps = %.5f" % (time.time() - t0, cfg["u0"], cfg["eps"]))
+    links = ok.to_device_complex(cfg["U"])
+    Ws = {}
+    pre_ms = {}
+    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
+        Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(DIMS, prec))
+        scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(DIMS))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ok.ok_precompute_W(DIMS, c, links, prec, Ws[prec], scr)
+        e1.record()
+        torch.cuda.synchronize()
+        pre_ms[PREC_NAME[prec]] = round(e0.elapsed_time(e1), 3)
+        del scr
+    log("precompute ms %s" % pre_ms)
+
+    # ---- timed region: M applied to the 12-RHS batch --------------------------------
+    sp = ok.OK_F64 if form == ok.OK_F64 else ok.OK_F32
+    dt = torch.float64 if sp == ok.OK_F64 else torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(I.SEED_SOURCES + 3)
+    x = torch.randn(NRHS * V * 24, dtype=dt, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ok.ok_apply_M(DIMS, c, Ws[form], form, x, y, sp, NRHS, stream)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_wall0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        ok.ok_apply_M(DIMS, c, Ws[form], form, x, y, sp, NRHS, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_per_step = float(np.mean(step_ms))
+    launch_ms = ms_per_step / NRHS                     # NRHS back-to-back kernel launches per step
+    bytes_launch = BYTES_SITE[form] * V
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    value = NRHS * bytes_launch / (ms_per_step * 1e-3) / 1e9
+    log("M.psi %s: %.3f ms/step (%d RHS), %.1f GB/s, %.1f%% of peak; wall %.3fs"
+        % (args.form, ms_per_step, NRHS, value, 100 * value / HBM_PEAK_GBS, t_wall))
+
+    # the other storage forms, one right-hand side each (context)
+    apply_forms = {}
+    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
+        spp = ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32
+        xx = x[: V * 24].to(torch.float64 if spp == ok.OK_F64 else torch.float32)
+        yy = torch.empty_like(xx)
+        for _ in range(2):
+            ok.ok_apply_M(DIMS, c, Ws[prec], prec, xx, yy, spp, 1, stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(10):
+            ok.ok_apply_M(DIMS, c, Ws[prec], prec, xx, yy, spp, 1, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 10
+        gbs = BYTES_SITE[prec] * V / (ms * 1e-3) / 1e9
+        apply_forms[PREC_NAME[prec]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                        "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "sites_per_s": round(V / (ms * 1e-3), 0)}
+
+    if args.copy_probe:
+        copy_probe()
+
+    # ---- time to solution: plain vs chosen, the 12 point sources --------------------
+    solve = None
+    if not args.no_solve:
+        xi = ok.to_device_complex(cfg["xi"])
+        res = {}
+        for name, low in (("plain", None), ("chosen", ok.OK_BF16)):
+            lp = -1 if low is None else low
+            work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(DIMS, NRHS, lp))
+            psi = torch.zeros_like(xi)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, st = ok.ok_bicgstab(DIMS, c, ok.SolverParams(tol=1e-10), Ws[ok.OK_F64],
+                                    None if low is None else Ws[low], lp, xi, psi, NRHS, work, stream)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t
+            res[name] = {
+                "seconds": round(sec, 3), "status": rc,
+                "iterations": int(sum(s["iterations"] for s in st)),
+                "matvec_f64": int(sum(s["matvec_hi"] for s in st)),
+                "matvec_low": int(sum(s["matvec_lo"] for s in st)),
+                "reliable_updates": int(sum(s["reliable_updates"] for s in st)),
+                "max_true_rel_resid": max(s["true_rel_resid"] for s in st),
+            }
+            log("solve %s: %s" % (name, res[name]))
+            del work, psi
+        solve = {"workload": "12 point sources to ||xi-M psi||/||xi|| <= 1e-10 (FP64 true residual)",
+                 "plain": dict(form="FP64 W, FP64 fields, one RHS after the other", **res["plain"]),
+                 "chosen": dict(form="BF16 W, FP32 fields, FP64 reliable updates, one RHS after the other",
+                                **res["chosen"]),
+                 "speedup": round(res["plain"]["seconds"] / res["chosen"]["seconds"], 3)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline()
+        log("cpu baseline %s" % cpu)
+
+    out = {
+        "metric": "M.psi HBM GB/s (% peak) at 20^3x64; time to 1e-10 residual, plain vs chosen",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16 W, f32 spinors, f32 accumulate"}[args.form],
+        "data": "synthetic: random SU(3) links at plaquette 0.6, 12 point sources; stand-in OK coefficients",
+        "config": {"workload": "OK operator M.psi, 20^3x64 lattice, 12 RHS, %s W (dense 27x12x12 per site)"
+                               % args.form, "lattice": list(DIMS), "nrhs": NRHS, "W_storage": args.form,
+                   "u0": round(cfg["u0"], 6), "eps": round(cfg["eps"], 6)},
+        "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(args.form),
+                     "kernel": "%s<%s>, %d sites, %d B/site" % (KERNEL_NAME, args.form, V, BYTES_SITE[form]),
+                     "launch_ms": round(launch_ms, 4)},
+        "apply_forms_1rhs": apply_forms,
+        "precompute_ms": pre_ms,
+        "time_to_solution": solve,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

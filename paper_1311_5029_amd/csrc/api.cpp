@@ -169,7 +169,7 @@ int okinv::stencil_tps(int Wprec) {
     const char* e = getenv("OKINV_TPS");
     const int over = e ? atoi(e) : 0;
     if (over == 1 || over == 2 || over == 4) return over;
-    return Wprec == OK_F64 ? 2 : 1;
+    return Wprec == OK_F32 ? 1 : 4;
 }
 
 extern "C" {
