@@ -6,10 +6,11 @@ the stand-in coefficient set at m0 a = 0.5, and the 12 spin-colour point
 sources at the origin.
 
 One step = one application of M (ok_apply_M) to the 12-right-hand-side batch,
-with the chosen storage of W (FP32 by default).  The metric is the HBM
-throughput of that application in algorithmic bytes (dense W streamed once per
-right-hand side applied + one spinor read and one written, per site), timed
-with HIP events on the stream the library launches on.  The second half of the
+with the chosen storage of W (FP32 by default), which runs the MFMA kernel
+(one launch for the 12 right-hand sides).  The metric is the HBM throughput of
+that application in algorithmic bytes (the dense W streamed once + 12 spinors
+read and 12 written, per site), timed with HIP events on the stream the
+library launches on.  The second half of the
 metric, time to ||xi - M psi||/||xi|| <= 1e-10, is measured on the same batch:
 "plain" = FP64 BiCGStab, one right-hand side after the other; "chosen" =
 BiCGStab in FP32 fields with BF16 W and FP64 reliable updates.
@@ -35,6 +36,9 @@ NRHS = 12
 # algorithmic bytes per site of one single-right-hand-side application: dense
 # 27 x 12x12 complex W + spinor in + spinor out
 BYTES_SITE = {0: 27 * 144 * 16 + 2 * 192, 1: 27 * 144 * 8 + 2 * 96, 2: 27 * 144 * 4 + 2 * 96}
+# ... and of one application to the 12-RHS batch by the MFMA kernel: W streamed
+# once for all right-hand sides + 12 spinors in and out (FP64 W: 12 single launches)
+BYTES_STEP = {0: NRHS * BYTES_SITE[0], 1: 27 * 144 * 8 + NRHS * 2 * 96, 2: 27 * 144 * 4 + NRHS * 2 * 96}
 PREC_NAME = {0: "f64", 1: "f32", 2: "bf16"}
 KERNEL_NAME = "k_apply"
 
@@ -45,16 +49,20 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("stencil.hip", "wlayout.h", "common.h"):
+    for f in ("stencil.hip", "stencil_mrhs.hip", "wlayout.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1311_5029_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(form):
+def traffic_path(kernel, form):
+    return os.path.join(ROOT, "profiles", "%s_%s_20x20x20x64_traffic.json" % (kernel, form))
+
+
+def load_traffic(kernel, form):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 PMC
     summary, or None when the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_apply_%s_20x20x20x64_traffic.json" % form)
+    path = traffic_path(kernel, form)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -67,10 +75,13 @@ def load_traffic(form):
 COPY_BYTES = 1 << 30
 
 
-def is_apply_kernel(name, form):
-    """Whether a (mangled or demangled) kernel name is the single-RHS apply of this form
-    without a reduction epilogue: k_apply<prec, threads-per-site, 0>."""
+def is_apply_kernel(name, form, kernel="k_apply"):
+    """Whether a (mangled or demangled) kernel name is the apply kernel of this form:
+    k_apply<prec, threads-per-site, 0> (single RHS, no reduction epilogue) or
+    k_apply_mrhs<prec> (the batched MFMA kernel)."""
     p = {"f64": 0, "f32": 1, "bf16": 2}[form]
+    if kernel == "k_apply_mrhs":
+        return ("k_apply_mrhs<%d>" % p) in name or ("k_apply_mrhsILi%dE" % p) in name
     return any(("k_apply<%d, %d, 0>" % (p, t)) in name or ("k_applyILi%dELi%dELi0E" % (p, t)) in name
                for t in (1, 2, 4))
 
@@ -104,31 +115,33 @@ def _read_counters(d):
 
 
 def parse_pmc(fetch_dir, write_dir, form):
-    """Average FETCH_SIZE + WRITE_SIZE (KiB per dispatch) of the dominant kernel,
-    each scaled by the same counter's reading for the 1 GiB copy; writes the
-    traffic summary consumed by the benchmark's roofline entry."""
-    res = {}
-    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        rows = _read_counters(d)
-        ker = [v[cname] for (k, _), v in rows.items() if cname in v and is_apply_kernel(k, form)]
-        cop = [v[cname] for (k, _), v in rows.items() if "copy" in k.lower() and cname in v]
-        cop = [x for x in cop if x * 1024 > 0.5 * COPY_BYTES]
-        if not ker or not cop:
-            raise SystemExit("no %s samples for the kernel or the copy in %s" % (cname, d))
-        scale = COPY_BYTES / (1024.0 * float(np.median(cop)))
-        res[cname] = {"kib_per_dispatch": float(np.mean(ker)), "dispatches": len(ker),
-                      "copy_kib": float(np.median(cop)), "scale": scale,
-                      "bytes_per_launch": float(np.mean(ker)) * 1024.0 * scale}
-    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    """Average FETCH_SIZE + WRITE_SIZE (KiB per dispatch) of each apply kernel of this
+    form, each counter scaled by its reading for the 1 GiB copy; writes one traffic
+    summary per kernel found (consumed by the benchmark's roofline entry)."""
     prec = {"f64": 0, "f32": 1, "bf16": 2}[form]
-    out = {"kernel": "%s<%s> (single RHS, no epilogue)" % (KERNEL_NAME, form), "lattice": list(DIMS),
-           "bytes_per_launch": total, "algorithmic_bytes_per_launch": BYTES_SITE[prec] * V,
-           "ratio_to_algorithmic": total / (BYTES_SITE[prec] * V), "counters": res,
-           "source_sha": source_hash()}
-    path = os.path.join(ROOT, "profiles", "k_apply_%s_20x20x20x64_traffic.json" % form)
-    with open(path, "w") as fh:
-        json.dump(out, fh, indent=1)
-    print(json.dumps(out, indent=1))
+    algo = {"k_apply": BYTES_SITE[prec] * V, "k_apply_mrhs": BYTES_STEP[prec] * V}
+    rows = {c: _read_counters(d) for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
+    for kernel in ("k_apply", "k_apply_mrhs"):
+        res = {}
+        for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+            ker = [v[cname] for (k, _), v in rows[cname].items() if cname in v and is_apply_kernel(k, form, kernel)]
+            cop = [v[cname] for (k, _), v in rows[cname].items() if "copy" in k.lower() and cname in v]
+            cop = [x for x in cop if x * 1024 > 0.5 * COPY_BYTES]
+            if not ker or not cop:
+                break
+            scale = COPY_BYTES / (1024.0 * float(np.median(cop)))
+            res[cname] = {"kib_per_dispatch": float(np.mean(ker)), "dispatches": len(ker),
+                          "copy_kib": float(np.median(cop)), "scale": scale,
+                          "bytes_per_launch": float(np.mean(ker)) * 1024.0 * scale}
+        if len(res) < 2:
+            continue
+        total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+        out = {"kernel": "%s<%s>" % (kernel, form), "lattice": list(DIMS), "bytes_per_launch": total,
+               "algorithmic_bytes_per_launch": algo[kernel], "ratio_to_algorithmic": total / algo[kernel],
+               "counters": res, "source_sha": source_hash()}
+        with open(traffic_path(kernel, form), "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(json.dumps(out, indent=1))
 
 
 def summarize_trace(d, out_path, command):
@@ -261,10 +274,11 @@ def main():
     t_wall = time.perf_counter() - t_wall0
     step_ms = [a.elapsed_time(b) for a, b in evs]
     ms_per_step = float(np.mean(step_ms))
-    launch_ms = ms_per_step / NRHS                     # NRHS back-to-back kernel launches per step
-    bytes_launch = BYTES_SITE[form] * V
+    launches = NRHS if form == ok.OK_F64 else 1        # FP64: one launch per right-hand side
+    launch_ms = ms_per_step / launches
+    bytes_launch = BYTES_STEP[form] * V / launches
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    value = NRHS * bytes_launch / (ms_per_step * 1e-3) / 1e9
+    value = BYTES_STEP[form] * V / (ms_per_step * 1e-3) / 1e9
     log("M.psi %s: %.3f ms/step (%d RHS), %.1f GB/s, %.1f%% of peak; wall %.3fs"
         % (args.form, ms_per_step, NRHS, value, 100 * value / HBM_PEAK_GBS, t_wall))
 
@@ -341,13 +355,16 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16 W, f32 spinors, f32 accumulate"}[args.form],
         "data": "synthetic: random SU(3) links at plaquette 0.6, 12 point sources; stand-in OK coefficients",
-        "config": {"workload": "OK operator M.psi, 20^3x64 lattice, 12 RHS, %s W (dense 27x12x12 per site)"
-                               % args.form, "lattice": list(DIMS), "nrhs": NRHS, "W_storage": args.form,
+        "config": {"workload": "OK operator M.psi, 20^3x64 lattice, 12 RHS batched, %s W (dense 27x12x12 "
+                               "per site)" % args.form, "lattice": list(DIMS), "nrhs": NRHS, "W_storage": args.form,
                    "u0": round(cfg["u0"], 6), "eps": round(cfg["eps"], 6)},
         "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(args.form),
-                     "kernel": "%s<%s>, %d sites, %d B/site" % (KERNEL_NAME, args.form, V, BYTES_SITE[form]),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic("k_apply" if form == ok.OK_F64 else "k_apply_mrhs",
+                                                                       args.form),
+                     "kernel": "%s<%s>, %d sites, %d B/site" % (
+                         "k_apply" if form == ok.OK_F64 else "k_apply_mrhs", args.form, V,
+                         BYTES_STEP[form] // launches),
                      "launch_ms": round(launch_ms, 4)},
         "apply_forms_1rhs": apply_forms,
         "precompute_ms": pre_ms,

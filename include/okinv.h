@@ -56,6 +56,21 @@ enum ok_status {
 /* Storage / arithmetic precision of W and of spinors. */
 enum ok_prec { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2 };
 
+/* Layout flag OR-ed into the W precision of ok_W_bytes, ok_precompute_W,
+ * ok_apply_M and ok_W_to_dense: the 27 blocks of each site stored
+ * contiguously (site-major), the layout the multi-right-hand-side MFMA
+ * kernel of ok_apply_M streams best.  Without it W is plane-major (each
+ * 16-byte piece of a block laid out over consecutive sites), best for one
+ * right-hand side.  Both layouts hold the same numbers; the flag is valid
+ * with OK_F32 and OK_BF16. */
+#define OK_LAYOUT_SITE 0x10
+
+/* Spinor layout flag OR-ed into spinor_prec of ok_apply_M (FP32 spinors,
+ * site-major W, nrhs <= 16): spinors stored [V][4][3][nrhs] complex, the
+ * right-hand side index fastest, which the multi-right-hand-side kernel reads
+ * contiguously.  Without it spinors are [nrhs][V][4][3]. */
+#define OK_SPINOR_RHS_INNER 0x20
+
 typedef struct ok_geom {
     int32_t L[4];           /* Lx, Ly, Lz, Lt */
 } ok_geom;
@@ -118,8 +133,12 @@ int ok_precompute_W(const ok_geom* g, const ok_coeffs* c, const double* d_links,
                     void* d_scratch, size_t scratch_bytes, void* stream);
 
 /* d_out = M d_psi for nrhs right-hand sides (Eq. minFlopForm with mhat from c).
- * Allowed (W_prec, spinor_prec): (F64, F64), (F32, F32), (BF16, F32).
- * Arithmetic is FP64 for FP64 W and FP32 (FP32 accumulation) otherwise.
+ * Allowed (W_prec, spinor_prec): (F64, F64), (F32, F32), (BF16, F32), each
+ * W precision optionally | OK_LAYOUT_SITE and, with it, the FP32 spinors
+ * optionally | OK_SPINOR_RHS_INNER.  Arithmetic is FP64 for FP64 W and FP32
+ * (FP32 accumulation) otherwise; with nrhs > 1 (and always with site-major W)
+ * FP32 and BF16 W run on the matrix cores, BF16 W multiplying the FP32
+ * spinor split into two bf16 terms (2^-16 relative).
  * d_out must not overlap d_psi.  Asynchronous on `stream`. */
 int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec,
                const void* d_psi, void* d_out, int spinor_prec, int nrhs, void* stream);

@@ -82,6 +82,13 @@ static int check_coeffs(const ok_coeffs* c) {
 
 static bool valid_prec(int p) { return p == OK_F64 || p == OK_F32 || p == OK_BF16; }
 
+// W precision with an optional OK_LAYOUT_SITE flag (FP32 and BF16 only)
+static bool valid_wprec(int p) {
+    const int b = p & ~OK_LAYOUT_SITE;
+    if (p & OK_LAYOUT_SITE) return b == OK_F32 || b == OK_BF16;
+    return valid_prec(b);
+}
+
 static size_t spinor_bytes(const Geo& g, int sprec) { return (size_t)g.V * 12 * (sprec == OK_F64 ? 16 : 8); }
 
 static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -108,15 +115,15 @@ const char* ok_last_error(void) { return g_err; }
 int ok_W_bytes(const ok_geom* g, int prec, size_t* bytes) {
     Geo G;
     OK_TRY(make_geo(g, &G));
-    if (!valid_prec(prec)) {
-        set_error("unknown precision %d", prec);
+    if (!valid_wprec(prec)) {
+        set_error("unknown W precision/layout %d", prec);
         return OK_EINVAL;
     }
     if (!bytes) {
         set_error("bytes is NULL");
         return OK_EINVAL;
     }
-    *bytes = w_bytes(prec, G.Vs);
+    *bytes = w_bytes(prec & ~OK_LAYOUT_SITE, G.Vs);
     return OK_SUCCESS;
 }
 
@@ -136,15 +143,16 @@ int ok_precompute_W(const ok_geom* g, const ok_coeffs* c, const double* d_links,
     Geo G;
     OK_TRY(make_geo(g, &G));
     OK_TRY(check_coeffs(c));
-    if (!valid_prec(prec)) {
-        set_error("unknown precision %d", prec);
+    if (!valid_wprec(prec)) {
+        set_error("unknown W precision/layout %d", prec);
         return OK_EINVAL;
     }
+    const size_t wb = w_bytes(prec & ~OK_LAYOUT_SITE, G.Vs);
     OK_TRY(check_ptr(d_links, "d_links"));
     OK_TRY(check_ptr(d_W, "d_W"));
     OK_TRY(check_ptr(d_scratch, "d_scratch"));
-    if (W_bytes < w_bytes(prec, G.Vs)) {
-        set_error("W buffer has %zu bytes, needs %zu", W_bytes, w_bytes(prec, G.Vs));
+    if (W_bytes < wb) {
+        set_error("W buffer has %zu bytes, needs %zu", W_bytes, wb);
         return OK_ESIZE;
     }
     const size_t need = (size_t)6 * 9 * 16 * G.Vs;
@@ -153,8 +161,7 @@ int ok_precompute_W(const ok_geom* g, const ok_coeffs* c, const double* d_links,
         return OK_ESIZE;
     }
     const size_t lb = (size_t)G.V * 4 * 9 * 16;
-    if (overlap(d_W, w_bytes(prec, G.Vs), d_links, lb) || overlap(d_scratch, need, d_links, lb) ||
-        overlap(d_W, w_bytes(prec, G.Vs), d_scratch, need)) {
+    if (overlap(d_W, wb, d_links, lb) || overlap(d_scratch, need, d_links, lb) || overlap(d_W, wb, d_scratch, need)) {
         set_error("d_W, d_scratch and d_links must not overlap");
         return OK_EINVAL;
     }
@@ -172,6 +179,13 @@ int okinv::stencil_tps(int Wprec) {
     return Wprec == OK_F32 ? 1 : 4;
 }
 
+// Multi-right-hand-side MFMA kernel for nrhs > 1 (OKINV_MRHS=0 selects one
+// single-right-hand-side launch per right-hand side instead).
+static bool use_mrhs() {
+    const char* e = getenv("OKINV_MRHS");
+    return !(e && e[0] == '0');
+}
+
 extern "C" {
 
 int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec, const void* d_psi, void* d_out,
@@ -179,12 +193,20 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
     Geo G;
     OK_TRY(make_geo(g, &G));
     OK_TRY(check_coeffs(c));
-    if (!valid_prec(W_prec)) {
-        set_error("unknown W precision %d", W_prec);
+    if (!valid_wprec(W_prec)) {
+        set_error("unknown W precision/layout %d", W_prec);
         return OK_EINVAL;
     }
-    const bool ok_pair = (W_prec == OK_F64 && spinor_prec == OK_F64) ||
-                         (W_prec != OK_F64 && spinor_prec == OK_F32);
+    const int wbase = W_prec & ~OK_LAYOUT_SITE;
+    const bool site_major = (W_prec & OK_LAYOUT_SITE) != 0;
+    const bool rhs_inner = (spinor_prec & OK_SPINOR_RHS_INNER) != 0;
+    if (rhs_inner && (!site_major || nrhs > 16)) {
+        set_error("OK_SPINOR_RHS_INNER needs site-major W (OK_LAYOUT_SITE) and nrhs <= 16");
+        return OK_EINVAL;
+    }
+    spinor_prec &= ~OK_SPINOR_RHS_INNER;
+    const bool ok_pair = (wbase == OK_F64 && spinor_prec == OK_F64) ||
+                         (wbase != OK_F64 && spinor_prec == OK_F32);
     if (!ok_pair) {
         set_error("unsupported (W_prec, spinor_prec) = (%d, %d)", W_prec, spinor_prec);
         return OK_EINVAL;
@@ -202,6 +224,12 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
         return OK_EINVAL;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (site_major)
+        return launch_apply_site(G, d_W, wbase, reinterpret_cast<const float*>(d_psi),
+                                 reinterpret_cast<float*>(d_out), c->mhat, nrhs, rhs_inner ? 1 : 0, st);
+    if (nrhs > 1 && W_prec != OK_F64 && use_mrhs())
+        return launch_apply_mrhs(G, d_W, W_prec, reinterpret_cast<const float*>(d_psi),
+                                 reinterpret_cast<float*>(d_out), c->mhat, nrhs, st);
     const int tps = stencil_tps(W_prec);
     for (int r = 0; r < nrhs; ++r) {
         const char* in = reinterpret_cast<const char*>(d_psi) + sb * r;
@@ -214,8 +242,8 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
 int ok_W_to_dense(const ok_geom* g, const void* d_W, int prec, double* d_dense, void* stream) {
     Geo G;
     OK_TRY(make_geo(g, &G));
-    if (!valid_prec(prec)) {
-        set_error("unknown precision %d", prec);
+    if (!valid_wprec(prec)) {
+        set_error("unknown W precision/layout %d", prec);
         return OK_EINVAL;
     }
     OK_TRY(check_ptr(d_W, "d_W"));

@@ -57,6 +57,15 @@ int apply_blocks(const Geo& g, int tps);
 int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int tps,
                  int epi, const void* aux, double2* partial, hipStream_t st);
 
+// stencil_mrhs.hip: up to 16 right-hand sides per pass on MFMA (FP32 or BF16 W, FP32 spinors)
+int launch_apply_mrhs(const Geo& g, const void* W, int Wprec, const float* psi, float* out, double mhat,
+                      int nrhs, hipStream_t st);
+
+// the same for site-major W (OK_LAYOUT_SITE), any nrhs >= 1; rhs_inner selects
+// spinors [V][12][nrhs] (nrhs <= 16) instead of [nrhs][V][12]
+int launch_apply_site(const Geo& g, const void* W, int Wprec, const float* psi, float* out, double mhat,
+                      int nrhs, int rhs_inner, hipStream_t st);
+
 // precompute.hip
 int launch_precompute(const Geo& g, const ok_coeffs& c, const double* links, int prec, void* W,
                       void* scratch, hipStream_t st);

@@ -268,7 +268,7 @@ constexpr int kPairJ[3] = {1, 2, 2};
 
 template <int P>
 __global__ void __launch_bounds__(64) k_forward(Geo g, PreCoef q, const double* links, const double2* F,
-                                                void* W) {
+                                                void* W, int layout) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     const int f = blockIdx.y;   // 0: W0, 1..3: W+_i, 4: W+_4, 5..7: W++_ii, 8..10: W++_ij, 11..13: W+-_ij
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(64) k_forward(Geo g, PreCoef q, const double* 
                 v[3 * be + b] = w1 * e1 + w2 * e2;
             }
         }
-        w_store_row<P>(W, Vs, k, 3 * al + a, s, v);
+        w_store_row<P>(W, Vs, layout, k, 3 * al + a, s, v);
     }
 }
 
@@ -428,7 +428,7 @@ constexpr int kBwd[13] = {5, 6, 7, 8, 12, 13, 14, 18, 19, 20, 24, 25, 26};
 constexpr int kFwdOf[13] = {1, 2, 3, 4, 9, 10, 11, 15, 16, 17, 21, 22, 23};
 
 template <int P>
-__global__ void __launch_bounds__(64) k_backward(Geo g, void* W) {
+__global__ void __launch_bounds__(64) k_backward(Geo g, void* W, int layout) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     const int kb = kBwd[blockIdx.y], kf = kFwdOf[blockIdx.y];
@@ -445,34 +445,35 @@ __global__ void __launch_bounds__(64) k_backward(Geo g, void* W) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             // Gamma(X)[(al,a),(be,b)] = sg * conj(X[(be^2, b), (al^2, a)])
-            c128 xv = w_load_entry<P>(W, g.Vs, kf, (3 * bep + b) * 12 + 3 * alp + a, src);
+            c128 xv = w_load_entry<P>(W, g.Vs, layout, kf, (3 * bep + b) * 12 + 3 * alp + a, src);
             v[3 * be + b] = c128{sg * xv.re, -sg * xv.im};
         }
     }
-    w_store_row<P>(W, g.Vs, kb, row, s, v);
+    w_store_row<P>(W, g.Vs, layout, kb, row, s, v);
 }
 
 // ------------------------------------------------------------------ dense expansion
 template <int P>
-__global__ void __launch_bounds__(64) k_to_dense(Geo g, const void* W, double2* dense) {
+__global__ void __launch_bounds__(64) k_to_dense(Geo g, const void* W, int layout, double2* dense) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     const int k = blockIdx.y, row = blockIdx.z;
 #pragma unroll
     for (int col = 0; col < 12; ++col) {
-        c128 v = w_load_entry<P>(W, g.Vs, k, row * 12 + col, s);
+        c128 v = w_load_entry<P>(W, g.Vs, layout, k, row * 12 + col, s);
         dense[((size_t)s * kW + k) * kWE + row * 12 + col] = make_double2(v.re, v.im);
     }
 }
 
 template <int P>
-int run_precompute(const Geo& g, const PreCoef& q, const double* links, void* W, double2* F, hipStream_t st) {
+int run_precompute(const Geo& g, const PreCoef& q, const double* links, void* W, int layout, double2* F,
+                   hipStream_t st) {
     const unsigned nb = grid_for(g.V, 64);
     k_clover<<<dim3(grid_for(g.V, 256), 6), 256, 0, st>>>(g, links, F);
     OK_LAUNCH_CHECK("k_clover");
-    k_forward<P><<<dim3(nb, 14, 3), 64, 0, st>>>(g, q, links, F, W);
+    k_forward<P><<<dim3(nb, 14, 3), 64, 0, st>>>(g, q, links, F, W, layout);
     OK_LAUNCH_CHECK("k_forward");
-    k_backward<P><<<dim3(nb, 13, 12), 64, 0, st>>>(g, W);
+    k_backward<P><<<dim3(nb, 13, 12), 64, 0, st>>>(g, W, layout);
     OK_LAUNCH_CHECK("k_backward");
     return OK_SUCCESS;
 }
@@ -496,20 +497,22 @@ int launch_precompute(const Geo& g, const ok_coeffs& c, const double* links, int
     q.cSii = (c.c_1 + 2.0 * c.c_2) * 0.5 / u0;
     q.cOff = c.c_2 * 0.5 / u0;
     double2* F = reinterpret_cast<double2*>(scratch);
-    switch (prec) {
-        case OK_F64: return run_precompute<OK_F64>(g, q, links, W, F, st);
-        case OK_F32: return run_precompute<OK_F32>(g, q, links, W, F, st);
-        default: return run_precompute<OK_BF16>(g, q, links, W, F, st);
+    const int layout = (prec & OK_LAYOUT_SITE) ? 1 : 0;
+    switch (prec & ~OK_LAYOUT_SITE) {
+        case OK_F64: return run_precompute<OK_F64>(g, q, links, W, layout, F, st);
+        case OK_F32: return run_precompute<OK_F32>(g, q, links, W, layout, F, st);
+        default: return run_precompute<OK_BF16>(g, q, links, W, layout, F, st);
     }
 }
 
 int launch_to_dense(const Geo& g, const void* W, int prec, double* dense, hipStream_t st) {
     dim3 grid(grid_for(g.V, 64), kW, 12);
     double2* d = reinterpret_cast<double2*>(dense);
-    switch (prec) {
-        case OK_F64: k_to_dense<OK_F64><<<grid, 64, 0, st>>>(g, W, d); break;
-        case OK_F32: k_to_dense<OK_F32><<<grid, 64, 0, st>>>(g, W, d); break;
-        default: k_to_dense<OK_BF16><<<grid, 64, 0, st>>>(g, W, d); break;
+    const int layout = (prec & OK_LAYOUT_SITE) ? 1 : 0;
+    switch (prec & ~OK_LAYOUT_SITE) {
+        case OK_F64: k_to_dense<OK_F64><<<grid, 64, 0, st>>>(g, W, layout, d); break;
+        case OK_F32: k_to_dense<OK_F32><<<grid, 64, 0, st>>>(g, W, layout, d); break;
+        default: k_to_dense<OK_BF16><<<grid, 64, 0, st>>>(g, W, layout, d); break;
     }
     OK_LAUNCH_CHECK("k_to_dense");
     return OK_SUCCESS;

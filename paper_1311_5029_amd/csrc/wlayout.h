@@ -7,7 +7,17 @@
 //
 //     cell(k, j, s) = base + ((k * chunks_per_block + j) * Vs + s) * 16 bytes
 //
-// so a wavefront of consecutive sites reads or writes 1 KiB contiguously.
+// so a wavefront of consecutive sites reads or writes 1 KiB contiguously
+// (plane layout, the default: best for one right-hand side).
+//
+// With OK_LAYOUT_SITE the 27 blocks of a site are contiguous instead:
+//
+//     cell(k, j, s) = base + ((s * 27 + k) * chunks_per_block + j) * 16 bytes
+//
+// which the multi-right-hand-side MFMA kernel streams one block at a time; in
+// that layout FP32 blocks are stored column-major (entry 12*col + row), the
+// order in which the lanes of the FP32 MFMA read their A operands, and BF16
+// blocks row-major (the BF16 MFMA reads 4 consecutive columns per lane).
 #pragma once
 
 #include "common.h"
@@ -31,6 +41,10 @@ template <> struct WL<OK_BF16> {
     static constexpr int esize = 4;
 };
 
+__host__ __device__ __forceinline__ size_t w_cell(int layout, int Vs, int ch, int k, int j, int s) {
+    return layout ? ((size_t)s * kW + k) * ch + j : ((size_t)(k * ch + j)) * Vs + s;
+}
+
 inline size_t w_bytes(int prec, int Vs) {
     size_t es = prec == OK_F64 ? 16 : prec == OK_F32 ? 8 : 4;
     return (size_t)kW * kWE * es * (size_t)Vs;
@@ -38,13 +52,21 @@ inline size_t w_bytes(int prec, int Vs) {
 
 // Store one row (12 complex, FP64 values) of block k at site s.
 template <int P>
-__device__ __forceinline__ void w_store_row(void* W, int Vs, int k, int row, int s, const c128 v[12]) {
+__device__ __forceinline__ void w_store_row(void* W, int Vs, int layout, int k, int row, int s, const c128 v[12]) {
     uint4* base = reinterpret_cast<uint4*>(W);
     constexpr int per = WL<P>::per, ch = WL<P>::chunks;
+    if constexpr (P == OK_F32) {
+        if (layout) {   // column-major block: entry (row, col) at 12*col + row
+            float2* b = reinterpret_cast<float2*>(base + w_cell(layout, Vs, ch, k, 0, s));
+#pragma unroll
+            for (int c = 0; c < 12; ++c) b[12 * c + row] = make_float2((float)v[c].re, (float)v[c].im);
+            return;
+        }
+    }
     const int j0 = row * 12 / per;
 #pragma unroll
     for (int q = 0; q < 12 / per; ++q) {
-        size_t cell = ((size_t)(k * ch + j0 + q)) * Vs + s;
+        size_t cell = w_cell(layout, Vs, ch, k, j0 + q, s);
         if constexpr (P == OK_F64) {
             double2 d = make_double2(v[q].re, v[q].im);
             reinterpret_cast<double2*>(base)[cell] = d;
@@ -67,9 +89,10 @@ __device__ __forceinline__ void w_store_row(void* W, int Vs, int k, int row, int
 
 // Load entry e (0..143) of block k at site s as FP64 (exact for every storage type).
 template <int P>
-__device__ __forceinline__ c128 w_load_entry(const void* W, int Vs, int k, int e, int s) {
+__device__ __forceinline__ c128 w_load_entry(const void* W, int Vs, int layout, int k, int e, int s) {
     constexpr int per = WL<P>::per, ch = WL<P>::chunks;
-    size_t cell = ((size_t)(k * ch + e / per)) * Vs + s;
+    if (P == OK_F32 && layout) e = 12 * (e % 12) + e / 12;   // column-major block
+    size_t cell = w_cell(layout, Vs, ch, k, e / per, s);
     if constexpr (P == OK_F64) {
         double2 d = reinterpret_cast<const double2*>(W)[cell];
         return c128{d.x, d.y};

@@ -21,6 +21,8 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 OK_F64, OK_F32, OK_BF16 = 0, 1, 2
+OK_LAYOUT_SITE = 0x10
+OK_SPINOR_RHS_INNER = 0x20
 OK_SUCCESS, OK_NOT_CONVERGED, OK_BREAKDOWN = 0, 1, 2
 OK_EINVAL, OK_ESIZE, OK_EALIGN, OK_EDEVICE, OK_ENONFINITE = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK_SUCCESS", 1: "OK_NOT_CONVERGED", 2: "OK_BREAKDOWN", -1: "OK_EINVAL",

@@ -57,14 +57,21 @@ class Lattice:
         ok.ok_apply_M(self.dims, c or self.c, self.precompute(prec), prec, psi_dev, out, sp, nrhs)
         return out
 
-    def apply(self, prec, psi, c=None):
-        """M psi for a host spinor psi (..., Lt, Lz, Ly, Lx, 4, 3); returns complex128."""
+    def apply(self, prec, psi, c=None, rhs_inner=False):
+        """M psi for a host spinor psi (..., Lt, Lz, Ly, Lx, 4, 3); returns complex128.
+        rhs_inner: pass the batch to the library with the right-hand side index fastest."""
         ok = self.ok
         nrhs = int(np.prod(psi.shape[:-6])) if psi.ndim > 6 else 1
-        d = ok.to_device_complex(psi, dtype=self.spinor_dtype(prec))
-        out = self.apply_dev(prec, d, nrhs, c)
+        host = np.moveaxis(psi, 0, -1) if rhs_inner else psi
+        d = ok.to_device_complex(np.ascontiguousarray(host), dtype=self.spinor_dtype(prec))
+        out = self.torch.empty_like(d)
+        sp = ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32
+        if rhs_inner:
+            sp |= ok.OK_SPINOR_RHS_INNER
+        ok.ok_apply_M(self.dims, c or self.c, self.precompute(prec), prec, d, out, sp, nrhs)
         self.torch.cuda.synchronize()
-        return ok.to_host_complex(out, psi.shape)
+        res = ok.to_host_complex(out, host.shape)
+        return np.moveaxis(res, -1, 0) if rhs_inner else res
 
 
 def rel(a, b):

@@ -96,6 +96,65 @@ def test_apply_matches_oracle(lat, prec, tps, monkeypatch):
     assert maxrel(got, ref) <= tol * (1.0 if prec == 0 else 3.0)
 
 
+@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [2, 12, 16, 20])
+def test_apply_batched_mfma_matches_oracle(lat, prec, nrhs):
+    """The multi-right-hand-side MFMA kernel (nrhs > 16 runs in groups of 16)."""
+    psi = I.gaussian_sources(lat.dims, nrhs, 40 + nrhs)
+    ref = lat.oracle_B.apply(psi)
+    got = lat.apply(prec, psi)
+    tol = TOL_APPLY[prec]
+    for k in range(nrhs):
+        assert rel(got[k], ref[k]) <= tol
+        assert maxrel(got[k], ref[k]) <= 3.0 * tol
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "bf16"])
+def test_apply_batched_equals_single(lat, prec, monkeypatch):
+    psi = I.gaussian_sources(lat.dims, 12, 43)
+    batched = lat.apply(prec, psi)
+    monkeypatch.setenv("OKINV_MRHS", "0")
+    single = lat.apply(prec, psi)
+    # same W and spinors, different FP32 summation order (each within ~5e-7 of exact);
+    # the BF16 kernel also splits the FP32 spinor into bf16 hi + lo (2^-18 per element)
+    assert rel(batched, single) <= (1e-6 if prec == 1 else 3e-5)
+
+
+SITE = 0x10   # OK_LAYOUT_SITE
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "bf16"])
+def test_site_layout_holds_same_numbers(lat, prec):
+    assert np.array_equal(lat.dense_W(prec | SITE), lat.dense_W(prec))
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [1, 2, 12, 16, 20])
+def test_apply_site_layout_matches_oracle(lat, prec, nrhs):
+    psi = I.gaussian_sources(lat.dims, nrhs, 50 + nrhs)
+    ref = lat.oracle_B.apply(psi)
+    got = lat.apply(prec | SITE, psi if nrhs > 1 else psi[0])
+    if nrhs == 1:
+        got = got[None]
+    tol = TOL_APPLY[prec]
+    for k in range(nrhs):
+        assert rel(got[k], ref[k]) <= tol
+        assert maxrel(got[k], ref[k]) <= 3.0 * tol
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [1, 5, 12, 16])
+def test_apply_site_rhs_inner_matches_oracle(lat, prec, nrhs):
+    """Site-major W with spinors [V][4][3][nrhs] (right-hand side fastest)."""
+    psi = I.gaussian_sources(lat.dims, nrhs, 60 + nrhs)
+    ref = lat.oracle_B.apply(psi)
+    got = lat.apply(prec | SITE, psi, rhs_inner=True)
+    tol = TOL_APPLY[prec]
+    for k in range(nrhs):
+        assert rel(got[k], ref[k]) <= tol
+        assert maxrel(got[k], ref[k]) <= 3.0 * tol
+
+
 def test_apply_multiple_rhs(lat):
     ok = lib()
     psi = I.gaussian_sources(lat.dims, 3, 22)
@@ -170,6 +229,23 @@ def test_full_size_sampled_sites(big, prec):
     ref = apply_at_sites(big.U, psi, big.c, sites)
     gs = np.stack([got[t, z, y, x] for (x, y, z, t) in sites])
     assert rel(gs, ref) <= TOL_APPLY[prec]
+
+
+@pytest.mark.parametrize("prec,inner", [(1, False), (2, False), (1 | SITE, False), (2 | SITE, False),
+                                        (1 | SITE, True), (2 | SITE, True)],
+                         ids=["f32", "bf16", "f32-site", "bf16-site", "f32-site-inner", "bf16-site-inner"])
+def test_full_size_batched_sampled_sites(big, prec, inner):
+    """12 right-hand sides through the MFMA kernels at 20^3 x 64, sampled sites vs the oracle."""
+    psi = I.gaussian_sources(big.dims, 12, 33).astype(np.complex64)
+    got = big.apply(prec, psi, rhs_inner=inner)
+    big.W.pop(prec, None)
+    rng = np.random.default_rng(8)
+    sites = [(0, 0, 0, 0), (19, 19, 19, 63)] + [tuple(int(v) for v in rng.integers(0, [20, 20, 20, 64]))
+                                                for _ in range(3)]
+    for k in (0, 5, 11):
+        ref = apply_at_sites(big.U, psi[k].astype(np.complex128), big.c, sites)
+        gs = np.stack([got[k, t, z, y, x] for (x, y, z, t) in sites])
+        assert rel(gs, ref) <= TOL_APPLY[prec & ~SITE]
 
 
 def test_full_size_gamma5_hermiticity(big):
