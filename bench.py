@@ -47,9 +47,11 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def source_hash():
+def source_hash(kernel="k_apply"):
+    """Hash of the sources of a kernel (its file plus the shared layout headers)."""
     h = hashlib.sha256()
-    for f in ("stencil.hip", "stencil_mrhs.hip", "wlayout.h", "common.h"):
+    main = "stencil.hip" if kernel == "k_apply" else "stencil_mrhs.hip"
+    for f in (main, "wlayout.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1311_5029_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -67,7 +69,7 @@ def load_traffic(kernel, form):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_sha") != source_hash():
+    if d.get("source_sha") != source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -77,9 +79,12 @@ COPY_BYTES = 1 << 30
 
 def is_apply_kernel(name, form, kernel="k_apply"):
     """Whether a (mangled or demangled) kernel name is the apply kernel of this form:
-    k_apply<prec, threads-per-site, 0> (single RHS, no reduction epilogue) or
-    k_apply_mrhs<prec> (the batched MFMA kernel)."""
+    k_apply<prec, threads-per-site, 0> (single RHS, no reduction epilogue),
+    k_apply_site<prec, 1> (the batched MFMA kernel, site-major W, RHS-inner spinors)
+    or k_apply_mrhs<prec> (batched, plane-major W)."""
     p = {"f64": 0, "f32": 1, "bf16": 2}[form]
+    if kernel == "k_apply_site":
+        return ("k_apply_site<%d, 1>" % p) in name or ("k_apply_siteILi%dELi1E" % p) in name
     if kernel == "k_apply_mrhs":
         return ("k_apply_mrhs<%d>" % p) in name or ("k_apply_mrhsILi%dE" % p) in name
     return any(("k_apply<%d, %d, 0>" % (p, t)) in name or ("k_applyILi%dELi%dELi0E" % (p, t)) in name
@@ -119,9 +124,10 @@ def parse_pmc(fetch_dir, write_dir, form):
     form, each counter scaled by its reading for the 1 GiB copy; writes one traffic
     summary per kernel found (consumed by the benchmark's roofline entry)."""
     prec = {"f64": 0, "f32": 1, "bf16": 2}[form]
-    algo = {"k_apply": BYTES_SITE[prec] * V, "k_apply_mrhs": BYTES_STEP[prec] * V}
+    algo = {"k_apply": BYTES_SITE[prec] * V, "k_apply_mrhs": BYTES_STEP[prec] * V,
+            "k_apply_site": BYTES_STEP[prec] * V}
     rows = {c: _read_counters(d) for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
-    for kernel in ("k_apply", "k_apply_mrhs"):
+    for kernel in ("k_apply", "k_apply_mrhs", "k_apply_site"):
         res = {}
         for cname in ("FETCH_SIZE", "WRITE_SIZE"):
             ker = [v[cname] for (k, _), v in rows[cname].items() if cname in v and is_apply_kernel(k, form, kernel)]
@@ -138,7 +144,7 @@ def parse_pmc(fetch_dir, write_dir, form):
         total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
         out = {"kernel": "%s<%s>" % (kernel, form), "lattice": list(DIMS), "bytes_per_launch": total,
                "algorithmic_bytes_per_launch": algo[kernel], "ratio_to_algorithmic": total / algo[kernel],
-               "counters": res, "source_sha": source_hash()}
+               "counters": res, "source_sha": source_hash(kernel)}
         with open(traffic_path(kernel, form), "w") as fh:
             json.dump(out, fh, indent=1)
         print(json.dumps(out, indent=1))
@@ -240,9 +246,11 @@ def main():
     c = cfg["coeffs"]
     log("links in %.1fs, plaquette^(1/4) = u0 = %.5f, eps = %.5f" % (time.time() - t0, cfg["u0"], cfg["eps"]))
     links = ok.to_device_complex(cfg["U"])
+    SITE, INNER = ok.OK_LAYOUT_SITE, ok.OK_SPINOR_RHS_INNER
     Ws = {}
     pre_ms = {}
-    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
+    wforms = [ok.OK_F64, ok.OK_F32, ok.OK_BF16, ok.OK_F32 | SITE, ok.OK_BF16 | SITE]
+    for prec in wforms:
         Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(DIMS, prec))
         scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(DIMS))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -250,31 +258,33 @@ def main():
         ok.ok_precompute_W(DIMS, c, links, prec, Ws[prec], scr)
         e1.record()
         torch.cuda.synchronize()
-        pre_ms[PREC_NAME[prec]] = round(e0.elapsed_time(e1), 3)
+        pre_ms[PREC_NAME[prec & 3] + ("_site" if prec & SITE else "")] = round(e0.elapsed_time(e1), 3)
         del scr
     log("precompute ms %s" % pre_ms)
 
     # ---- timed region: M applied to the 12-RHS batch --------------------------------
-    sp = ok.OK_F64 if form == ok.OK_F64 else ok.OK_F32
-    dt = torch.float64 if sp == ok.OK_F64 else torch.float32
-    gen = torch.Generator(device="cuda").manual_seed(I.SEED_SOURCES + 3)
-    x = torch.randn(NRHS * V * 24, dtype=dt, device="cuda", generator=gen)
-    y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda").manual_seed(I.SEED_SOURCES + 3)
+    if form == ok.OK_F64:    # no FP64 matrix-core kernel: 12 single-RHS launches (plane W)
+        wprec, sprec, launches, kname = ok.OK_F64, ok.OK_F64, NRHS, "k_apply"
+        x = torch.randn(NRHS * V * 24, dtype=torch.float64, device="cuda", generator=gen)
+    else:
+        wprec, sprec, launches, kname = form | SITE, ok.OK_F32 | INNER, 1, "k_apply_site"
+        x = torch.randn(NRHS * V * 24, dtype=torch.float32, device="cuda", generator=gen)
+    y = torch.empty_like(x)
     for _ in range(args.warmup):
-        ok.ok_apply_M(DIMS, c, Ws[form], form, x, y, sp, NRHS, stream)
+        ok.ok_apply_M(DIMS, c, Ws[wprec], wprec, x, y, sprec, NRHS, stream)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t_wall0 = time.perf_counter()
     for a, b in evs:
         a.record(stream)
-        ok.ok_apply_M(DIMS, c, Ws[form], form, x, y, sp, NRHS, stream)
+        ok.ok_apply_M(DIMS, c, Ws[wprec], wprec, x, y, sprec, NRHS, stream)
         b.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall0
     step_ms = [a.elapsed_time(b) for a, b in evs]
     ms_per_step = float(np.mean(step_ms))
-    launches = NRHS if form == ok.OK_F64 else 1        # FP64: one launch per right-hand side
     launch_ms = ms_per_step / launches
     bytes_launch = BYTES_STEP[form] * V / launches
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
@@ -282,25 +292,35 @@ def main():
     log("M.psi %s: %.3f ms/step (%d RHS), %.1f GB/s, %.1f%% of peak; wall %.3fs"
         % (args.form, ms_per_step, NRHS, value, 100 * value / HBM_PEAK_GBS, t_wall))
 
-    # the other storage forms, one right-hand side each (context)
-    apply_forms = {}
-    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
-        spp = ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32
-        xx = x[: V * 24].to(torch.float64 if spp == ok.OK_F64 else torch.float32)
+    def time_apply(wp, sp, nrhs, n=10):
+        dt = torch.float64 if sp == ok.OK_F64 else torch.float32
+        xx = x[: nrhs * V * 24].to(dt)
         yy = torch.empty_like(xx)
         for _ in range(2):
-            ok.ok_apply_M(DIMS, c, Ws[prec], prec, xx, yy, spp, 1, stream)
+            ok.ok_apply_M(DIMS, c, Ws[wp], wp, xx, yy, sp, nrhs, stream)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        for _ in range(10):
-            ok.ok_apply_M(DIMS, c, Ws[prec], prec, xx, yy, spp, 1, stream)
+        for _ in range(n):
+            ok.ok_apply_M(DIMS, c, Ws[wp], wp, xx, yy, sp, nrhs, stream)
         b.record(stream)
         torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / 10
+        return a.elapsed_time(b) / n
+
+    # context: one right-hand side (plane W), and the batched forms
+    apply_forms = {}
+    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
+        ms = time_apply(prec, ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32, 1)
         gbs = BYTES_SITE[prec] * V / (ms * 1e-3) / 1e9
-        apply_forms[PREC_NAME[prec]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
-                                        "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                        "sites_per_s": round(V / (ms * 1e-3), 0)}
+        apply_forms["1rhs_" + PREC_NAME[prec]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                                  "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                                  "rhs_sites_per_s": round(V / (ms * 1e-3), 0)}
+    for prec in (ok.OK_F32, ok.OK_BF16):
+        ms = time_apply(prec | SITE, ok.OK_F32 | INNER, NRHS)
+        gbs = BYTES_STEP[prec] * V / (ms * 1e-3) / 1e9
+        apply_forms["12rhs_mfma_" + PREC_NAME[prec]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                                        "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                                        "rhs_sites_per_s": round(NRHS * V / (ms * 1e-3), 0)}
+    log("apply forms %s" % apply_forms)
 
     if args.copy_probe:
         copy_probe()
@@ -310,7 +330,7 @@ def main():
     if not args.no_solve:
         xi = ok.to_device_complex(cfg["xi"])
         res = {}
-        for name, low in (("plain", None), ("chosen", ok.OK_BF16)):
+        for name, low in (("plain", None), ("chosen", ok.OK_BF16 | SITE)):
             lp = -1 if low is None else low
             work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(DIMS, NRHS, lp))
             psi = torch.zeros_like(xi)
@@ -332,8 +352,8 @@ def main():
             del work, psi
         solve = {"workload": "12 point sources to ||xi-M psi||/||xi|| <= 1e-10 (FP64 true residual)",
                  "plain": dict(form="FP64 W, FP64 fields, one RHS after the other", **res["plain"]),
-                 "chosen": dict(form="BF16 W, FP32 fields, FP64 reliable updates, one RHS after the other",
-                                **res["chosen"]),
+                 "chosen": dict(form="12 RHS together: BF16 W on the matrix cores, FP32 fields, "
+                                     "FP64 reliable updates", **res["chosen"]),
                  "speedup": round(res["plain"]["seconds"] / res["chosen"]["seconds"], 3)}
 
     cpu = None
@@ -355,18 +375,15 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16 W, f32 spinors, f32 accumulate"}[args.form],
         "data": "synthetic: random SU(3) links at plaquette 0.6, 12 point sources; stand-in OK coefficients",
-        "config": {"workload": "OK operator M.psi, 20^3x64 lattice, 12 RHS batched, %s W (dense 27x12x12 "
-                               "per site)" % args.form, "lattice": list(DIMS), "nrhs": NRHS, "W_storage": args.form,
+        "config": {"workload": "OK operator M.psi, 20^3x64 lattice, 12 RHS batched on the matrix cores, %s W "
+                               "(dense 27x12x12 per site, site-major)" % args.form, "lattice": list(DIMS), "nrhs": NRHS, "W_storage": args.form,
                    "u0": round(cfg["u0"], 6), "eps": round(cfg["eps"], 6)},
         "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic("k_apply" if form == ok.OK_F64 else "k_apply_mrhs",
-                                                                       args.form),
-                     "kernel": "%s<%s>, %d sites, %d B/site" % (
-                         "k_apply" if form == ok.OK_F64 else "k_apply_mrhs", args.form, V,
-                         BYTES_STEP[form] // launches),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kname, args.form),
+                     "kernel": "%s<%s>, %d sites, %d B/site" % (kname, args.form, V, BYTES_STEP[form] // launches),
                      "launch_ms": round(launch_ms, 4)},
-        "apply_forms_1rhs": apply_forms,
+        "apply_forms": apply_forms,
         "precompute_ms": pre_ms,
         "time_to_solution": solve,
         "cpu_baseline": cpu,

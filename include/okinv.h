@@ -152,11 +152,16 @@ int ok_W_to_dense(const ok_geom* g, const void* d_W, int prec, double* d_dense, 
 int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t* bytes);
 
 /* Solve M psi = xi for nrhs right-hand sides by BiCGStab (Sec. 2.3).
- *   d_W64   FP64 W (always needed: residuals and the final check are FP64).
+ *   d_W64   FP64 W, plane layout (always needed: residuals and the final
+ *           check are FP64).
  *   d_Wlo   NULL: plain FP64 BiCGStab.  Otherwise W at Wlo_prec (OK_F32 or
  *           OK_BF16): the iteration runs in FP32 fields with that operator and
  *           FP64 reliable updates (x accumulated and r recomputed in FP64 when
- *           the low-precision residual drops by params->delta).
+ *           the low-precision residual drops by params->delta).  With
+ *           Wlo_prec | OK_LAYOUT_SITE the right-hand sides (in groups of up to
+ *           16) iterate together: one matrix-core application of W per
+ *           BiCGStab step for the whole group, per-right-hand-side scalars,
+ *           reliable updates and convergence.
  *   d_xi    FP64 source [nrhs][V][4][3] complex.
  *   d_psi   FP64 [nrhs][V][4][3]: the initial guess unless params->zero_guess,
  *           the solution on return.

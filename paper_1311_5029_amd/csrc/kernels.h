@@ -98,4 +98,34 @@ int launch_zero(const Geo& g, bool f64, void* dst, hipStream_t st);
 // partial <a, a> of an FP64 field (norm of the source)
 int launch_norm64(const Geo& g, const double* a, double2* partial, hipStream_t st);
 
+// blas1_batched.hip -- a batch of right-hand sides iterating together (FP32 fields, right-hand side
+// index fastest: element (12 * site + component) * nrhs + j)
+constexpr int kMaxRhsB = 16;
+constexpr int kGridB = 1024;     // fixed grid of the batched vector kernels
+struct ScalB {
+    double2 rho[kMaxRhsB], rho_old[kMaxRhsB], alpha[kMaxRhsB], omega[kMaxRhsB], beta[kMaxRhsB];
+    double rr[kMaxRhsB], rr_true[kMaxRhsB];
+    int flags[kMaxRhsB], active[kMaxRhsB];
+};
+int batch_rows(const Geo& g);
+int col_blocks(const Geo& g);
+int launch_bp_update(const Geo& g, int nrhs, float* p, const float* r, const float* v, const ScalB* sc,
+                     hipStream_t st);
+int launch_bs_update(const Geo& g, int nrhs, float* s, const float* r, const float* v, const ScalB* sc,
+                     hipStream_t st);
+int launch_bxr_update(const Geo& g, int nrhs, float* x, float* r, const float* p, const float* s, const float* t,
+                      const float* rhat, const ScalB* sc, double2* partial, hipStream_t st);
+int launch_bdot(const Geo& g, int nrhs, const float* a, const float* b, const ScalB* sc, double2* partial,
+                hipStream_t st);
+int launch_bfinish(int kind, int nblocks, int j0, int nj, const double2* partial, ScalB* sc, hipStream_t st);
+int launch_col_accum(const Geo& g, int nrhs, int j, double* x64, float* x32, hipStream_t st);
+int launch_col_residual(const Geo& g, int nrhs, int j, const double* xi, const double* t64, float* r32,
+                        double2* partial, hipStream_t st);
+int launch_col_norm64(const Geo& g, int j, const double* a, double2* partial, hipStream_t st);
+int launch_col_load(const Geo& g, int nrhs, int j, const double* a, float* r32, hipStream_t st);
+int launch_col_restart(const Geo& g, int nrhs, int j, const float* r, float* rhat, float* p, float* v,
+                       hipStream_t st);
+int launch_col_dot(const Geo& g, int nrhs, int j, const float* a, const float* b, double2* partial,
+                   hipStream_t st);
+
 }  // namespace okinv

@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 
 #include "common.h"
 #include "kernels.h"
@@ -277,6 +278,208 @@ int solve_mixed(Ctx& C, const double* xi, double* x64, ok_solver_stats* S) {
     }
 }
 
+// ------------------------------------------------------------------ batched
+// All right-hand sides (up to 16) iterate together: one MFMA application of the
+// low-precision site-major W per BiCGStab step for the whole batch, FP32 fields
+// with the right-hand side index fastest, per-right-hand-side scalars, and FP64
+// reliable updates per right-hand side (column) when its residual has dropped
+// by delta.  Converged right-hand sides stop updating; the operator still runs
+// over every column.
+struct WorkB {
+    ScalB* sc;
+    double2* partial;
+    double* t64;
+    float* f[7];   // x32 r rhat p v s t
+};
+
+size_t layout_batched(const Geo& g, int nrhs, char* base, WorkB* w) {
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        char* p = base ? base + off : nullptr;
+        off += align256(n);
+        return p;
+    };
+    WorkB tmp;
+    WorkB& W = w ? *w : tmp;
+    W.sc = reinterpret_cast<ScalB*>(take(sizeof(ScalB)));
+    const int nb = std::max(kGridB, col_blocks(g));
+    W.partial = reinterpret_cast<double2*>(take((size_t)nb * kMaxRhsB * 2 * sizeof(double2)));
+    W.t64 = reinterpret_cast<double*>(take((size_t)g.V * 12 * 16));
+    for (int i = 0; i < 7; ++i) W.f[i] = reinterpret_cast<float*>(take((size_t)g.V * 12 * nrhs * 8));
+    return off;
+}
+
+int bfin(Ctx& C, WorkB& B, int kind, int nb, int j0, int nj) {
+    return launch_bfinish(kind, nb, j0, nj, B.partial, B.sc, C.st);
+}
+
+int read_scalb(Ctx& C, WorkB& B, ScalB* h) {
+    OK_HIP(hipMemcpyAsync(h, B.sc, sizeof(ScalB), hipMemcpyDeviceToHost, C.st));
+    OK_HIP(hipStreamSynchronize(C.st));
+    return OK_SUCCESS;
+}
+
+int write_active(Ctx& C, WorkB& B, const ScalB* h) {
+    OK_HIP(hipMemcpyAsync(B.sc->active, h->active, sizeof(h->active), hipMemcpyHostToDevice, C.st));
+    OK_HIP(hipStreamSynchronize(C.st));
+    return OK_SUCCESS;
+}
+
+// x64_j += x32[:, j]; r[:, j] = xi_j - M64 x64_j; returns ||r_j||^2 (FP64)
+int batched_true_residual(Ctx& C, WorkB& B, int nrhs, int j, const double* xi, double* x64, double* rr,
+                          ok_solver_stats* S) {
+    const Geo& g = C.g;
+    OK_TRY(launch_col_accum(g, nrhs, j, x64, B.f[0], C.st));
+    OK_TRY(launch_apply(g, C.W64, OK_F64, x64, B.t64, C.c->mhat, C.tps64, EPI_NONE, nullptr, nullptr, C.st));
+    S->matvec_hi++;
+    OK_TRY(launch_col_residual(g, nrhs, j, xi, B.t64, B.f[1], B.partial, C.st));
+    OK_TRY(bfin(C, B, FIN_TRUE, col_blocks(g), j, 1));
+    ScalB h;
+    OK_TRY(read_scalb(C, B, &h));
+    *rr = h.rr_true[j];
+    return OK_SUCCESS;
+}
+
+int batched_restart(Ctx& C, WorkB& B, int nrhs, int j) {
+    const Geo& g = C.g;
+    OK_TRY(launch_col_restart(g, nrhs, j, B.f[1], B.f[2], B.f[3], B.f[4], C.st));
+    OK_TRY(launch_col_dot(g, nrhs, j, B.f[2], B.f[1], B.partial, C.st));
+    return bfin(C, B, FIN_INIT, col_blocks(g), j, 1);
+}
+
+// xi, x: FP64 [nrhs][V][12]; S: nrhs stats.  Returns the first failing status.
+int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_solver_stats* S) {
+    const ok_solver_params& P = *C.p;
+    const Geo& g = C.g;
+    const size_t fb = (size_t)g.V * 12 * nrhs * 8;
+    const size_t col = (size_t)g.V * 24;   // doubles per right-hand side in the ABI layout
+    float *x32 = B.f[0], *r = B.f[1], *rhat = B.f[2], *p = B.f[3], *v = B.f[4], *s = B.f[5], *t = B.f[6];
+    OK_HIP(hipMemsetAsync(B.sc, 0, sizeof(ScalB), C.st));
+    OK_HIP(hipMemsetAsync(x32, 0, fb, C.st));
+    OK_HIP(hipMemsetAsync(p, 0, fb, C.st));
+    OK_HIP(hipMemsetAsync(v, 0, fb, C.st));
+    OK_HIP(hipMemsetAsync(r, 0, fb, C.st));
+    OK_HIP(hipMemsetAsync(rhat, 0, fb, C.st));
+    ScalB h;
+    memset(&h, 0, sizeof(h));
+    double xn[kMaxRhsB], maxr[kMaxRhsB];
+    int rc_all = OK_SUCCESS;
+    for (int j = 0; j < nrhs; ++j) {
+        OK_TRY(launch_col_norm64(g, j, xi + j * col, B.partial, C.st));
+        OK_TRY(bfin(C, B, FIN_TRUE, col_blocks(g), j, 1));
+        ScalB h0;
+        OK_TRY(read_scalb(C, B, &h0));
+        xn[j] = std::sqrt(h0.rr_true[j]);
+        if (!std::isfinite(xn[j])) {
+            set_error("source %d is not finite", j);
+            S[j].status = OK_ENONFINITE;
+            return OK_ENONFINITE;
+        }
+        if (xn[j] == 0.0) {
+            OK_HIP(hipMemsetAsync(x + j * col, 0, col * 8, C.st));
+            S[j].true_rel_resid = 0.0;
+            S[j].status = OK_SUCCESS;
+            continue;
+        }
+        double rr;
+        if (P.zero_guess) {
+            OK_HIP(hipMemsetAsync(x + j * col, 0, col * 8, C.st));
+            OK_TRY(launch_col_load(g, nrhs, j, xi + j * col, r, C.st));
+            rr = xn[j] * xn[j];
+        } else {
+            OK_TRY(batched_true_residual(C, B, nrhs, j, xi + j * col, x + j * col, &rr, &S[j]));
+        }
+        S[j].true_rel_resid = std::sqrt(rr) / xn[j];
+        if (S[j].true_rel_resid <= P.tol) {
+            S[j].status = OK_SUCCESS;
+            continue;
+        }
+        h.active[j] = 1;
+        OK_HIP(hipMemcpyAsync(&B.sc->active[j], &h.active[j], sizeof(int), hipMemcpyHostToDevice, C.st));
+        OK_TRY(batched_restart(C, B, nrhs, j));
+        maxr[j] = std::sqrt(rr);
+    }
+    OK_TRY(write_active(C, B, &h));
+    auto any_active = [&]() {
+        for (int j = 0; j < nrhs; ++j)
+            if (h.active[j]) return true;
+        return false;
+    };
+    int it = 0;
+    const int wp = C.Wlo_prec & ~OK_LAYOUT_SITE;
+    while (any_active()) {
+        if (it >= P.max_iter) {
+            for (int j = 0; j < nrhs; ++j) {
+                if (!h.active[j]) continue;
+                double rr;
+                OK_TRY(batched_true_residual(C, B, nrhs, j, xi + j * col, x + j * col, &rr, &S[j]));
+                S[j].true_rel_resid = std::sqrt(rr) / xn[j];
+                S[j].status = S[j].true_rel_resid <= P.tol ? OK_SUCCESS : OK_NOT_CONVERGED;
+                if (S[j].status != OK_SUCCESS && rc_all == OK_SUCCESS) rc_all = S[j].status;
+                h.active[j] = 0;
+            }
+            break;
+        }
+        OK_TRY(launch_bp_update(g, nrhs, p, r, v, B.sc, C.st));
+        OK_TRY(launch_apply_site(g, C.Wlo, wp, p, v, C.c->mhat, nrhs, 1, C.st));
+        OK_TRY(launch_bdot(g, nrhs, rhat, v, B.sc, B.partial, C.st));
+        OK_TRY(bfin(C, B, FIN_ALPHA, kGridB, 0, nrhs));
+        OK_TRY(launch_bs_update(g, nrhs, s, r, v, B.sc, C.st));
+        OK_TRY(launch_apply_site(g, C.Wlo, wp, s, t, C.c->mhat, nrhs, 1, C.st));
+        OK_TRY(launch_bdot(g, nrhs, t, s, B.sc, B.partial, C.st));
+        OK_TRY(bfin(C, B, FIN_OMEGA, kGridB, 0, nrhs));
+        OK_TRY(launch_bxr_update(g, nrhs, x32, r, p, s, t, rhat, B.sc, B.partial, C.st));
+        OK_TRY(bfin(C, B, FIN_RHO, kGridB, 0, nrhs));
+        ScalB hd;
+        OK_TRY(read_scalb(C, B, &hd));
+        ++it;
+        bool changed = false;
+        for (int j = 0; j < nrhs; ++j) {
+            if (!h.active[j]) continue;
+            S[j].iterations++;
+            S[j].matvec_lo += 2;
+            const double rn = std::sqrt(hd.rr[j]);
+            if (P.verbose) fprintf(stderr, "okinv batched it %d rhs %d |r|/|xi| %.3e\n", it, j, rn / xn[j]);
+            if (!std::isfinite(rn)) {
+                set_error("residual of right-hand side %d became non-finite at iteration %d", j, it);
+                S[j].status = OK_ENONFINITE;
+                return OK_ENONFINITE;
+            }
+            const bool broke = hd.flags[j] & 1;
+            maxr[j] = std::max(maxr[j], rn);
+            if (!(rn < P.delta * maxr[j] || rn / xn[j] <= P.tol || broke)) continue;
+            double rr;
+            OK_TRY(batched_true_residual(C, B, nrhs, j, xi + j * col, x + j * col, &rr, &S[j]));
+            S[j].reliable_updates++;
+            const double rt = std::sqrt(rr);
+            S[j].true_rel_resid = rt / xn[j];
+            if (S[j].true_rel_resid <= P.tol) {
+                S[j].status = OK_SUCCESS;
+                h.active[j] = 0;
+                changed = true;
+                continue;
+            }
+            maxr[j] = rt;
+            if (broke) {
+                if (S[j].restarts >= P.max_restarts) {
+                    S[j].status = OK_BREAKDOWN;
+                    if (rc_all == OK_SUCCESS) rc_all = OK_BREAKDOWN;
+                    h.active[j] = 0;
+                    changed = true;
+                    continue;
+                }
+                S[j].restarts++;
+                OK_TRY(batched_restart(C, B, nrhs, j));
+            } else {
+                OK_TRY(launch_col_dot(g, nrhs, j, rhat, r, B.partial, C.st));
+                OK_TRY(bfin(C, B, FIN_RHO_REPLACE, col_blocks(g), j, 1));
+            }
+        }
+        if (changed) OK_TRY(write_active(C, B, &h));
+    }
+    return rc_all;
+}
+
 }  // namespace
 }  // namespace okinv
 
@@ -292,11 +495,15 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t
         set_error("nrhs must be >= 1 and bytes non-NULL");
         return OK_EINVAL;
     }
-    if (Wlo_prec >= 0 && Wlo_prec != OK_F32 && Wlo_prec != OK_BF16) {
-        set_error("Wlo_prec must be OK_F32, OK_BF16 or negative (plain FP64)");
+    const int wb = Wlo_prec & ~OK_LAYOUT_SITE;
+    if (Wlo_prec >= 0 && wb != OK_F32 && wb != OK_BF16) {
+        set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE), or negative (plain FP64)");
         return OK_EINVAL;
     }
-    *bytes = layout(G, Wlo_prec >= 0, nullptr, nullptr);
+    if (Wlo_prec >= 0 && (Wlo_prec & OK_LAYOUT_SITE))
+        *bytes = layout_batched(G, std::min(nrhs, kMaxRhsB), nullptr, nullptr);
+    else
+        *bytes = layout(G, Wlo_prec >= 0, nullptr, nullptr);
     return OK_SUCCESS;
 }
 
@@ -324,14 +531,17 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
         return OK_EINVAL;
     }
     const bool mixed = d_Wlo != nullptr;
-    if (mixed && Wlo_prec != OK_F32 && Wlo_prec != OK_BF16) {
-        set_error("Wlo_prec must be OK_F32 or OK_BF16 when d_Wlo is given");
+    const int wlb = Wlo_prec & ~OK_LAYOUT_SITE;
+    if (mixed && wlb != OK_F32 && wlb != OK_BF16) {
+        set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE) when d_Wlo is given");
         return OK_EINVAL;
     }
+    const bool batched = mixed && (Wlo_prec & OK_LAYOUT_SITE);
     if ((rc = check_ptr(d_W64, "d_W64")) || (mixed && (rc = check_ptr(d_Wlo, "d_Wlo"))) ||
         (rc = check_ptr(d_xi, "d_xi")) || (rc = check_ptr(d_psi, "d_psi")) || (rc = check_ptr(d_work, "d_work")))
         return rc;
-    const size_t need = layout(C.g, mixed, nullptr, nullptr);
+    const size_t need = batched ? layout_batched(C.g, std::min(nrhs, kMaxRhsB), nullptr, nullptr)
+                                : layout(C.g, mixed, nullptr, nullptr);
     if (work_bytes < need) {
         set_error("workspace has %zu bytes, needs %zu", work_bytes, need);
         return OK_ESIZE;
@@ -344,7 +554,11 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
             return OK_EINVAL;
         }
     }
-    layout(C.g, mixed, reinterpret_cast<char*>(d_work), &C.w);
+    WorkB B;
+    if (batched)
+        layout_batched(C.g, std::min(nrhs, kMaxRhsB), reinterpret_cast<char*>(d_work), &B);
+    else
+        layout(C.g, mixed, reinterpret_cast<char*>(d_work), &C.w);
     C.c = c;
     C.p = p;
     C.W64 = d_W64;
@@ -352,8 +566,22 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
     C.Wlo_prec = Wlo_prec;
     C.st = reinterpret_cast<hipStream_t>(stream);
     C.tps64 = stencil_tps(OK_F64);
-    C.tpslo = mixed ? stencil_tps(Wlo_prec) : 1;
+    C.tpslo = mixed ? stencil_tps(wlb) : 1;
     int first_bad = OK_SUCCESS;
+    if (batched) {
+        for (int k0 = 0; k0 < nrhs; k0 += kMaxRhsB) {
+            const int nk = std::min(kMaxRhsB, nrhs - k0);
+            const auto tk = std::chrono::steady_clock::now();
+            for (int k = 0; k < nk; ++k) stats[k0 + k] = ok_solver_stats{};
+            const size_t off = (size_t)k0 * C.g.V * 24;
+            rc = solve_batched(C, B, nk, d_xi + off, d_psi + off, stats + k0);
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - tk).count();
+            for (int k = 0; k < nk; ++k) stats[k0 + k].seconds = sec;
+            if (rc < 0) return rc;
+            if (rc != OK_SUCCESS && first_bad == OK_SUCCESS) first_bad = rc;
+        }
+        return first_bad;
+    }
     for (int k = 0; k < nrhs; ++k) {
         const auto tk = std::chrono::steady_clock::now();
         ok_solver_stats& S = stats[k];

@@ -157,3 +157,78 @@ def test_pure_gauge_point_sources_fft():
     exact = pure_gauge_point_solution(dims, c, g, xi[:, 0, 0, 0, 0])
     for k in range(12):
         assert np.linalg.norm(x[k] - exact[k]) / np.linalg.norm(exact[k]) < 1e-8
+
+
+# --- batched: right-hand sides iterating together on the site-major MFMA operator ----------
+SITE = 0x10
+
+
+@pytest.mark.parametrize("low", [1, 2], ids=["f32", "bf16"])
+def test_batched_c1_twelve_sources(c1, low):
+    ok = lib()
+    xi = I.gaussian_sources(c1.dims, 12, 71)
+    rc, st, x = solve(c1, xi, low=low | SITE)
+    assert rc == ok.OK_SUCCESS and len(st) == 12
+    for k in range(12):
+        assert st[k]["status"] == 0 and st[k]["reliable_updates"] >= 1
+        assert oracle_resid(c1.U, c1.c, xi[k], x[k]) <= ORACLE_SLACK * TOL
+
+
+def test_batched_zero_source_and_groups_of_16():
+    """20 right-hand sides (two groups), one of them zero."""
+    ok = lib()
+    dims = (5, 6, 7, 4)
+    U = I.random_su3_links(dims, 0.3, 17)
+    c = I.standin_coeffs(m0=0.5, u0=I.tadpole_u0(U))
+    L = Lattice(dims, U, c)
+    xi = I.gaussian_sources(dims, 20, 72)
+    xi[3] = 0.0
+    rc, st, x = solve(L, xi, low=ok.OK_BF16 | SITE)
+    assert rc == ok.OK_SUCCESS
+    assert np.all(x[3] == 0) and st[3]["iterations"] == 0
+    for k in range(20):
+        if k != 3:
+            assert oracle_resid(U, c, xi[k], x[k]) <= ORACLE_SLACK * TOL
+
+
+def test_batched_max_iter_not_converged(c1):
+    ok = lib()
+    xi = I.gaussian_sources(c1.dims, 4, 73)
+    rc, st, x = solve(c1, xi, low=ok.OK_F32 | SITE, params=ok.SolverParams(tol=TOL, max_iter=2))
+    assert rc == ok.OK_NOT_CONVERGED
+    assert all(s["status"] == ok.OK_NOT_CONVERGED and s["iterations"] == 2 for s in st)
+
+
+def test_batched_deterministic(c1):
+    ok = lib()
+    xi = I.gaussian_sources(c1.dims, 12, 74)
+    _, _, a = solve(c1, xi, low=ok.OK_BF16 | SITE)
+    _, _, b = solve(c1, xi, low=ok.OK_BF16 | SITE)
+    assert np.array_equal(a, b)
+
+
+def test_batched_pure_gauge_point_sources_fft():
+    ok = lib()
+    dims = (8, 8, 8, 12)
+    U, g = I.pure_gauge_links(dims, 51)
+    c = I.standin_coeffs(m0=0.5, u0=1.0)
+    L = Lattice(dims, U, c)
+    xi = I.point_sources(dims)
+    rc, st, x = solve(L, xi, low=ok.OK_BF16 | SITE)
+    assert rc == ok.OK_SUCCESS
+    exact = pure_gauge_point_solution(dims, c, g, xi[:, 0, 0, 0, 0])
+    for k in range(12):
+        assert np.linalg.norm(x[k] - exact[k]) / np.linalg.norm(exact[k]) < 1e-8
+
+
+def test_batched_plaquette06_point_sources():
+    """The C3 link ensemble and point sources at a reduced 8^3 x 16 volume."""
+    ok = lib()
+    dims = (8, 8, 8, 16)
+    cfg = I.make_config("C3", dims=dims)
+    L = Lattice(dims, cfg["U"], cfg["coeffs"])
+    xi = cfg["xi"]
+    rc, st, x = solve(L, xi, low=ok.OK_BF16 | SITE)
+    assert rc == ok.OK_SUCCESS
+    for k in (0, 4, 11):
+        assert oracle_resid(cfg["U"], cfg["coeffs"], xi[k], x[k]) <= ORACLE_SLACK * TOL
