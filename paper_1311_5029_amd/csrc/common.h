@@ -133,6 +133,30 @@ __host__ __device__ __forceinline__ float bf16_to_f32(uint32_t h) {
     return __builtin_bit_cast(float, h << 16);
 }
 
+// ---------------------------------------------------------------- streaming loads
+// W is read exactly once per application: load it non-temporally so that it
+// does not evict the reused neighbour spinors from L2.
+typedef unsigned nt_u4 __attribute__((ext_vector_type(4)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+    const nt_u4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+    const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    return make_double2(v.x, v.y);
+}
+
 // ---------------------------------------------------------------- launches
 inline unsigned grid_for(long n, int block) { return (unsigned)((n + block - 1) / block); }
 

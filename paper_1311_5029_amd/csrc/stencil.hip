@@ -54,14 +54,14 @@ __device__ __forceinline__ void block_rows(const void* __restrict__ W, int Vs, i
         for (int j = 0; j < 12 / per; ++j) {
             const size_t cell = ((size_t)(k * ch + row * (12 / per) + j)) * Vs + s;
             if constexpr (P == OK_F64) {
-                double2 w = reinterpret_cast<const double2*>(W)[cell];
+                double2 w = ld_stream(reinterpret_cast<const double2*>(W) + cell);
                 cfma(acc[q], cpx<T>{w.x, w.y}, v[j]);
             } else if constexpr (P == OK_F32) {
-                float4 w = reinterpret_cast<const float4*>(W)[cell];
+                float4 w = ld_stream(reinterpret_cast<const float4*>(W) + cell);
                 cfma(acc[q], cpx<T>{w.x, w.y}, v[2 * j]);
                 cfma(acc[q], cpx<T>{w.z, w.w}, v[2 * j + 1]);
             } else {
-                uint4 w = reinterpret_cast<const uint4*>(W)[cell];
+                uint4 w = ld_stream(reinterpret_cast<const uint4*>(W) + cell);
                 const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {

@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(BS, 2) k_apply_mrhs(Geo g, const uint4* __rest
             const int cell = threadIdx.x + BS * n;
             const int ch = cell / TS, st = cell % TS;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (cell < NCELL && s0 + st < g.V) v = W[((size_t)(k * CH + ch)) * g.Vs + s0 + st];
+            if (cell < NCELL && s0 + st < g.V) v = ld_stream(W + ((size_t)(k * CH + ch)) * g.Vs + s0 + st);
             stage[n] = v;
         }
     };
@@ -297,14 +297,14 @@ __device__ __forceinline__ void load_ops(Ops<P>& o, const uint4* __restrict__ wk
         const float2* pa = reinterpret_cast<const float2*>(wk);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            o.a[q] = pa[lo.a[q]];
+            o.a[q] = ld_stream(pa + lo.a[q]);
             o.b[q] = SL ? sp[lo.b[q]] : sp[4 * q + grp];
         }
     } else {
 #pragma unroll
         for (int m = 0; m < 4; ++m) o.x[m] = sp[lo.b[m]];
-        o.w0 = wk[lo.a[0]];
-        o.w1 = wk[lo.a1];
+        o.w0 = ld_stream(wk + lo.a[0]);
+        o.w1 = ld_stream(wk + lo.a1);
     }
 }
 
