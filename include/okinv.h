@@ -7,7 +7,9 @@
  *
  * with the 12x12 spin-colour precalculation matrices W (Sec. 2.2,
  * Eqs. shifted_W_first..shifted_W_last) built once per gauge field, and solves
- * M psi = xi (Eq. dslash) by BiCGStab (Sec. 2.3).
+ * M psi = xi (Eq. dslash) by BiCGStab (Sec. 2.3), optionally right-preconditioned
+ * by a learned gauge-covariant linear stencil network (an addition to the
+ * paper's method, declared at the end of this header).
  *
  * Conventions shared by every call:
  *   - Geometry: L = (Lx, Ly, Lz, Lt), every L >= 3, periodic in all four
@@ -39,7 +41,7 @@
 extern "C" {
 #endif
 
-#define OKINV_ABI_VERSION 1
+#define OKINV_ABI_VERSION 2
 
 /* Status codes.  0 success, > 0 solver outcomes (stats filled), < 0 errors. */
 enum ok_status {
@@ -90,6 +92,10 @@ typedef struct ok_solver_params {
     int32_t max_restarts;   /* restarts after breakdown or residual drift        */
     int32_t zero_guess;     /* 1: start from psi = 0; 0: use d_psi as the guess  */
     int32_t verbose;        /* 1: print one line per iteration to stderr         */
+    int32_t stall_window;   /* > 0: in a preconditioned solve, a residual with no
+                               new minimum for this many iterations is a stall
+                               and hands over to the unpreconditioned solve;
+                               0: off                                           */
 } ok_solver_params;
 
 typedef struct ok_solver_stats {
@@ -99,6 +105,9 @@ typedef struct ok_solver_stats {
     int32_t matvec_lo;      /* low-precision applications of M                   */
     int32_t reliable_updates;
     int32_t restarts;
+    int32_t net_applies;    /* applications of the preconditioner network        */
+    int32_t fallbacks;      /* 1 if the preconditioned solve failed and the
+                               unpreconditioned one continued from its iterate   */
     double true_rel_resid;  /* ||xi - M64 psi|| / ||xi||, FP64, at return       */
     double seconds;         /* wall time of the call                             */
 } ok_solver_stats;
@@ -147,9 +156,13 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
  * inspection and tests).  Asynchronous on `stream`. */
 int ok_W_to_dense(const ok_geom* g, const void* d_W, int prec, double* d_dense, void* stream);
 
+typedef struct ok_net ok_net;
+
 /* Workspace bytes of ok_bicgstab for nrhs right-hand sides; Wlo_prec < 0 means
- * plain FP64 (no low-precision operator). */
-int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t* bytes);
+ * plain FP64 (no low-precision operator); net as passed to ok_bicgstab (NULL:
+ * no preconditioner). */
+int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const ok_net* net,
+                                size_t* bytes);
 
 /* Solve M psi = xi for nrhs right-hand sides by BiCGStab (Sec. 2.3).
  *   d_W64   FP64 W, plane layout (always needed: residuals and the final
@@ -162,6 +175,16 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t
  *           16) iterate together: one matrix-core application of W per
  *           BiCGStab step for the whole group, per-right-hand-side scalars,
  *           reliable updates and convergence.
+ *   net     NULL, or the learned preconditioner N (low-precision solves
+ *           only): BiCGStab then runs right-preconditioned, each step
+ *           applying N to the search direction and to s (p^ = N p,
+ *           v = M p^, s^ = N s, t = M s^, x += alpha p^ + omega s^), so the
+ *           residual and the stopping test stay those of M psi = xi.  If that
+ *           recurrence breaks down, stalls (params->stall_window) or meets a
+ *           non-finite value, the unpreconditioned solve continues from the
+ *           last FP64 iterate with the remaining iterations
+ *           (stats.fallbacks = 1).  The network needs d_Wlo (OK_EINVAL
+ *           otherwise).
  *   d_xi    FP64 source [nrhs][V][4][3] complex.
  *   d_psi   FP64 [nrhs][V][4][3]: the initial guess unless params->zero_guess,
  *           the solution on return.
@@ -170,9 +193,108 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t
  * Synchronous: returns after every right-hand side converged or failed.
  * Returns OK_SUCCESS if all converged, else the first failing status. */
 int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
-                const void* d_W64, const void* d_Wlo, int Wlo_prec,
+                const void* d_W64, const void* d_Wlo, int Wlo_prec, const ok_net* net,
                 const double* d_xi, double* d_psi, int nrhs,
                 void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------ learned preconditioner
+ *
+ * Not part of the paper's method: a gauge-covariant linear stencil network N,
+ * trained so that N xi approximates M^{-1} xi, used as the right
+ * preconditioner of ok_bicgstab.  One layer maps a spinor field phi to
+ *
+ *   phi'_x = sum_{k=0}^{26} A_k P_k(x) phi_{x+d_k}
+ *
+ * over the 27 offsets of Eq. minFlopForm, with A_k a 4x4 complex spin matrix
+ * (colour blind) and P_k(x) the colour transport along hop k: 1 for k = 0,
+ * U_mu(x) for +mu, U_i(x) U_i(x+i) for +2i, the mean of the two L-shaped
+ * two-link paths for +i+j and +i-j (the paths of the off-axis W blocks,
+ * Eqs. shifted_W_first..last), and P_{-d}(x) = P_d(x-d)^dag.  Each P_k(x)
+ * transforms as g(x) P_k(x) g(x+d_k)^dag, so N is gauge covariant.  N is a
+ * chain of n_layers layers.
+ *
+ *   Parameters: FP32 complex [n_layers][27][4][4] (A_k[spin out][spin in]).
+ *   Transports: the 13 forward P_k per site, FP32, private layout
+ *               (ok_net_transports).
+ *   Fields:     FP32 complex batches of nfields spinor fields,
+ *               [nfields][V][4][3], or with OK_SPINOR_RHS_INNER in flags
+ *               [V][4][3][nfields].
+ * Gradients are Wirtinger derivatives dL/d(conj A) of the real loss L; the
+ * gradient with respect to (Re A, Im A) is twice that. */
+#define OK_NET_MAX_LAYERS 16
+#define OK_NET_ADJOINT 0x40     /* flag of ok_net_layer: apply the adjoint layer */
+
+struct ok_net {
+    int32_t n_layers;           /* 1 .. OK_NET_MAX_LAYERS                        */
+    int32_t reserved;           /* 0                                             */
+    const float* d_params;      /* [n_layers][27][4][4] complex FP32             */
+    const float* d_T;           /* transports of the current gauge field         */
+};
+
+typedef struct ok_adam_cfg {
+    double lr, beta1, beta2, eps;   /* e.g. 1e-3, 0.9, 0.999, 1e-8                */
+} ok_adam_cfg;
+
+/* Real (FP32) parameter count of an n_layers network: n_layers * 27 * 16 * 2. */
+int ok_net_param_count(int n_layers, size_t* n_floats);
+
+/* Bytes of the transport buffer (13 x 9 complex FP32 per site, padded). */
+int ok_net_transports_bytes(const ok_geom* g, size_t* bytes);
+
+/* Build the transports from FP64 links [V][4][3][3] (FP64 products, stored
+ * FP32).  Redo it whenever the links change.  Asynchronous. */
+int ok_net_transports(const ok_geom* g, const double* d_links, float* d_T, size_t T_bytes, void* stream);
+
+/* One layer: d_out = sum_k A_k P_k d_in_{x+d_k} with d_A = [27][4][4] complex
+ * FP32; with OK_NET_ADJOINT in flags the adjoint layer
+ * sum_k P_{-k} A_k^dag d_in_{x-d_k}.  d_out must not overlap d_in.
+ * Asynchronous. */
+int ok_net_layer(const ok_geom* g, const float* d_A, const float* d_T, const float* d_in, float* d_out,
+                 int nfields, int flags, void* stream);
+
+/* Workspace bytes: training = 0 for ok_net_apply (ping-pong fields),
+ * 1 for ok_net_loss_and_grad / ok_net_train_step (every layer's output, the
+ * gradient partial sums and the loss scratch), 2 for ok_net_layer_wgrad and
+ * ok_net_loss_grad alone. */
+int ok_net_workspace_bytes(const ok_geom* g, int n_layers, int nfields, int training, size_t* bytes);
+
+/* d_out = N d_in.  Asynchronous. */
+int ok_net_apply(const ok_geom* g, const ok_net* net, const float* d_in, float* d_out, int nfields,
+                 int flags, void* d_work, size_t work_bytes, void* stream);
+
+/* Weight gradient of one layer: d_gA[k][a][b] = sum over fields, sites x and
+ * colour c of d_gout_x^{a c} conj((P_k d_in_{x+d_k})^{b c}), [27][4][4]
+ * complex FP32, summed in a fixed order (bitwise reproducible).
+ * Asynchronous. */
+int ok_net_layer_wgrad(const ok_geom* g, const float* d_T, const float* d_gout, const float* d_in,
+                       float* d_gA, int nfields, int flags, void* d_work, size_t work_bytes, void* stream);
+
+/* Loss L = (1/nfields) sum_f ||out_f - psi_f||^2 / ||psi_f||^2 (fields with
+ * psi_f = 0 contribute 0) into *d_loss (FP64, device), and its gradient
+ * d_gout = dL/d(conj out) = (out_f - psi_f) / (nfields ||psi_f||^2).  d_gout
+ * may equal d_out.  Asynchronous. */
+int ok_net_loss_grad(const ok_geom* g, const float* d_out, const float* d_psi, float* d_gout, double* d_loss,
+                     int nfields, int flags, void* d_work, size_t work_bytes, void* stream);
+
+/* Forward pass of N on the batch d_xi, the loss against d_psi into *d_loss and
+ * the gradient dL/d(conj params) into d_grad ([n_layers][27][4][4] complex
+ * FP32).  Asynchronous. */
+int ok_net_loss_and_grad(const ok_geom* g, const ok_net* net, const float* d_xi, const float* d_psi,
+                         int nfields, int flags, double* d_loss, float* d_grad, void* d_work, size_t work_bytes,
+                         void* stream);
+
+/* Adam on n real parameters d_p with Wirtinger gradient d_g (the real
+ * gradient is 2 d_g) and moments d_m, d_v (zero before step 1); step >= 1.
+ * Asynchronous. */
+int ok_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, size_t n, const ok_adam_cfg* cfg,
+                 int step, void* stream);
+
+/* One training step: ok_net_loss_and_grad, then ok_adam_step on the
+ * parameters of an n_layers network.  d_grad receives the gradient.
+ * Asynchronous. */
+int ok_net_train_step(const ok_geom* g, int n_layers, float* d_params, float* d_m, float* d_v, const float* d_T,
+                      const float* d_xi, const float* d_psi, int nfields, int flags, const ok_adam_cfg* cfg,
+                      int step, double* d_loss, float* d_grad, void* d_work, size_t work_bytes, void* stream);
 
 #ifdef __cplusplus
 }

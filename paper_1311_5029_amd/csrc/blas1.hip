@@ -68,8 +68,8 @@ __global__ void __launch_bounds__(BS) k_s_update(int n, T* s_, const T* r, const
 
 // x += alpha p + omega s ; r = s - omega t ; partial <r^, r>, <r, r>
 template <typename T>
-__global__ void __launch_bounds__(BS) k_xr_update(int n, T* x, T* r, const T* p, const T* s_, const T* t,
-                                                  const T* rhat, const Scal* sc, double2* partial) {
+__global__ void __launch_bounds__(BS) k_xr_update(int n, T* x, T* r, const T* p, const T* sx, const T* s_,
+                                                  const T* t, const T* rhat, const Scal* sc, double2* partial) {
     const int s = blockIdx.x * BS + threadIdx.x;
     double2 d1{0, 0}, d2{0, 0};
     if (s < n) {
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(BS) k_xr_update(int n, T* x, T* r, const T* p,
         for (int c = 0; c < 12; ++c) {
             const size_t i = (size_t)s * 12 + c;
             const cpx<T> sv = ld(s_, i);
-            st(x, i, ld(x, i) + alpha * ld(p, i) + omega * sv);
+            st(x, i, ld(x, i) + alpha * ld(p, i) + omega * ld(sx, i));
             const cpx<T> rv = sv - omega * ld(t, i);
             st(r, i, rv);
             dotacc(d1, ld(rhat, i), rv);
@@ -242,14 +242,16 @@ int launch_s_update(const Geo& g, bool f64, void* s, const void* r, const void* 
     return OK_SUCCESS;
 }
 
-int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, const void* s, const void* t,
-                     const void* rhat, const Scal* sc, double2* partial, hipStream_t st) {
+int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, const void* sx, const void* s,
+                     const void* t, const void* rhat, const Scal* sc, double2* partial, hipStream_t st) {
     if (f64)
         k_xr_update<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(x), tp<double>(r), tp<double>(p),
-                                                              tp<double>(s), tp<double>(t), tp<double>(rhat), sc, partial);
+                                                              tp<double>(sx), tp<double>(s), tp<double>(t),
+                                                              tp<double>(rhat), sc, partial);
     else
         k_xr_update<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(x), tp<float>(r), tp<float>(p),
-                                                             tp<float>(s), tp<float>(t), tp<float>(rhat), sc, partial);
+                                                             tp<float>(sx), tp<float>(s), tp<float>(t),
+                                                             tp<float>(rhat), sc, partial);
     OK_LAUNCH_CHECK("k_xr_update");
     return OK_SUCCESS;
 }

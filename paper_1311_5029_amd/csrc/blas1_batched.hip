@@ -77,8 +77,8 @@ __global__ void __launch_bounds__(BS) kb_s_update(int rows, int nrhs, float* s, 
 
 // x += alpha p + omega s ; r = s - omega t ; partial <r^, r>, <r, r>
 __global__ void __launch_bounds__(BS) kb_xr_update(int rows, int nrhs, float* x, float* r, const float* p,
-                                                   const float* s, const float* t, const float* rhat,
-                                                   const ScalB* sc, double2* partial) {
+                                                   const float* sx, const float* s, const float* t,
+                                                   const float* rhat, const ScalB* sc, double2* partial) {
     const int j = threadIdx.x & 15;
     double2 d1{0, 0}, d2{0, 0};
     if (j < nrhs && sc->active[j]) {
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(BS) kb_xr_update(int rows, int nrhs, float* x,
         for (int row = blockIdx.x * 16 + (threadIdx.x >> 4); row < rows; row += gridDim.x * 16) {
             const size_t i = (size_t)row * nrhs + j;
             const c64 sv = ldc(s, i);
-            stc(x, i, ldc(x, i) + alpha * ldc(p, i) + omega * sv);
+            stc(x, i, ldc(x, i) + alpha * ldc(p, i) + omega * ldc(sx, i));
             const c64 rv = sv - omega * ldc(t, i);
             stc(r, i, rv);
             dacc(d1, ldc(rhat, i), rv);
@@ -278,9 +278,9 @@ int launch_bs_update(const Geo& g, int nrhs, float* s, const float* r, const flo
     OK_LAUNCH_CHECK("kb_s_update");
     return OK_SUCCESS;
 }
-int launch_bxr_update(const Geo& g, int nrhs, float* x, float* r, const float* p, const float* s, const float* t,
-                      const float* rhat, const ScalB* sc, double2* partial, hipStream_t st) {
-    kb_xr_update<<<kGridB, BS, 0, st>>>(batch_rows(g), nrhs, x, r, p, s, t, rhat, sc, partial);
+int launch_bxr_update(const Geo& g, int nrhs, float* x, float* r, const float* p, const float* sx, const float* s,
+                      const float* t, const float* rhat, const ScalB* sc, double2* partial, hipStream_t st) {
+    kb_xr_update<<<kGridB, BS, 0, st>>>(batch_rows(g), nrhs, x, r, p, sx, s, t, rhat, sc, partial);
     OK_LAUNCH_CHECK("kb_xr_update");
     return OK_SUCCESS;
 }

@@ -158,6 +158,15 @@ __device__ __forceinline__ double2 ld_stream(const double2* p) {
 }
 
 // ---------------------------------------------------------------- launches
+// The hardware places workgroup b on XCD b % 8.  Hand each XCD a contiguous
+// range of the n tiles so that neighbouring sites are served by the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b & 7, q = b >> 3;
+    int start = 0;
+    for (int y = 0; y < x; ++y) start += (n - y + 7) >> 3;
+    return start + q;
+}
+
 inline unsigned grid_for(long n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace okinv

@@ -83,8 +83,9 @@ int blas_blocks(const Geo& g);
 // fields of 12 V complex of type T (double or float)
 int launch_p_update(const Geo& g, bool f64, void* p, const void* r, const void* v, const Scal* sc, hipStream_t st);
 int launch_s_update(const Geo& g, bool f64, void* s, const void* r, const void* v, const Scal* sc, hipStream_t st);
-int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, const void* s, const void* t,
-                     const void* rhat, const Scal* sc, double2* partial, hipStream_t st);
+// x += alpha p + omega sx ; r = s - omega t ; partial <r^, r>, <r, r>  (sx = s unless preconditioned)
+int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, const void* sx, const void* s,
+                     const void* t, const void* rhat, const Scal* sc, double2* partial, hipStream_t st);
 int launch_dot_rr(const Geo& g, bool f64, const void* rhat, const void* r, double2* partial, hipStream_t st);
 int launch_finish(int kind, int nblocks, const double2* partial, Scal* sc, hipStream_t st);
 enum Finish { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_RHO_REPLACE = 3, FIN_INIT = 4, FIN_TRUE = 5 };
@@ -113,8 +114,8 @@ int launch_bp_update(const Geo& g, int nrhs, float* p, const float* r, const flo
                      hipStream_t st);
 int launch_bs_update(const Geo& g, int nrhs, float* s, const float* r, const float* v, const ScalB* sc,
                      hipStream_t st);
-int launch_bxr_update(const Geo& g, int nrhs, float* x, float* r, const float* p, const float* s, const float* t,
-                      const float* rhat, const ScalB* sc, double2* partial, hipStream_t st);
+int launch_bxr_update(const Geo& g, int nrhs, float* x, float* r, const float* p, const float* sx, const float* s,
+                      const float* t, const float* rhat, const ScalB* sc, double2* partial, hipStream_t st);
 int launch_bdot(const Geo& g, int nrhs, const float* a, const float* b, const ScalB* sc, double2* partial,
                 hipStream_t st);
 int launch_bfinish(int kind, int nblocks, int j0, int nj, const double2* partial, ScalB* sc, hipStream_t st);
@@ -127,5 +128,27 @@ int launch_col_restart(const Geo& g, int nrhs, int j, const float* r, float* rha
                        hipStream_t st);
 int launch_col_dot(const Geo& g, int nrhs, int j, const float* a, const float* b, double2* partial,
                    hipStream_t st);
+
+// net.hip -- the learned preconditioner (FP32 fields, [nf][V][12] or with inner [V][12][nf])
+size_t net_T_bytes(const Geo& g);
+int net_wgrad_chunks(const Geo& g, int nf);
+size_t net_wgrad_partial_bytes(const Geo& g, int nf);
+size_t net_loss_partial_bytes(int nf);
+int launch_net_transports(const Geo& g, const double* links, float* T, hipStream_t st);
+int launch_net_layer(const Geo& g, int nf, bool inner, bool adjoint, const float* A, const float* T,
+                     const float* in, float* out, hipStream_t st);
+// gA = weight gradient of one layer; partial holds net_wgrad_partial_bytes
+int launch_net_wgrad(const Geo& g, int nf, bool inner, const float* T, const float* gout, const float* in,
+                     float* partial, float* gA, hipStream_t st);
+// loss and gout = dL/d(conj out); scratch holds net_loss_partial_bytes
+int launch_net_loss_grad(const Geo& g, int nf, bool inner, const float* out, const float* psi, float* gout,
+                         double* loss, void* scratch, hipStream_t st);
+int launch_adam(long n, float* p, const float* g, float* m, float* v, const ok_adam_cfg& c, int step,
+                hipStream_t st);
+
+// net_api.cpp -- the whole network on nf fields (work: net_apply_work_bytes)
+size_t net_apply_work_bytes(const Geo& g, int n_layers, int nf);
+int net_apply(const Geo& g, int n_layers, const float* params, const float* T, const float* in, float* out, int nf,
+              bool inner, void* work, hipStream_t st);
 
 }  // namespace okinv

@@ -13,6 +13,14 @@
 // its maximum since the last update, x64 += x32, r = xi - M64 x64 in FP64 and
 // the recurrence continues from that residual.  Convergence is always decided
 // by the FP64 true residual ||xi - M64 x|| / ||xi||.
+//
+// Right preconditioning by the learned network N (low-precision solves only):
+// the same recurrence on M N y = xi with x = N y carried directly, i.e.
+//   p^ = N p, v = M p^, s^ = N s, t = M s^, x += alpha p^ + omega s^,
+// so r stays the residual of M x = xi and the reliable updates and the
+// stopping test are unchanged.  A breakdown, a stall or a non-finite value in
+// the preconditioned recurrence hands the right-hand side to the
+// unpreconditioned solve, which continues from the last FP64 iterate.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,19 +36,23 @@
 namespace okinv {
 namespace {
 
+// internal outcome of a preconditioned solve: continue without the network
+constexpr int kFallback = 100;
+
 struct Work {
     Scal* sc;
     double2* partial;
     int npart;
     // FP64 fields (plain: r rhat p v s t ; mixed: r64 t64)
     double* f64[6];
-    // FP32 fields (mixed: xlo r rhat p v s t)
-    float* f32[7];
+    // FP32 fields (mixed: xlo r rhat p v s t ; with a network also p^ s^)
+    float* f32[9];
+    void* netw;   // network ping-pong fields
 };
 
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
-size_t layout(const Geo& g, bool mixed, char* base, Work* w) {
+size_t layout(const Geo& g, bool mixed, int net_layers, char* base, Work* w) {
     const int tps = std::max(stencil_tps(OK_F64), stencil_tps(OK_F32));
     const int npart = std::max({apply_blocks(g, 1), apply_blocks(g, 2), apply_blocks(g, 4), blas_blocks(g), tps});
     size_t off = 0;
@@ -61,8 +73,9 @@ size_t layout(const Geo& g, bool mixed, char* base, Work* w) {
         for (int i = 0; i < 6; ++i) W.f64[i] = reinterpret_cast<double*>(take(s64));
     } else {
         for (int i = 0; i < 2; ++i) W.f64[i] = reinterpret_cast<double*>(take(s64));
-        for (int i = 0; i < 7; ++i) W.f32[i] = reinterpret_cast<float*>(take(s32));
+        for (int i = 0; i < (net_layers ? 9 : 7); ++i) W.f32[i] = reinterpret_cast<float*>(take(s32));
     }
+    W.netw = net_layers ? take(net_apply_work_bytes(g, net_layers, 1)) : nullptr;
     return off;
 }
 
@@ -79,10 +92,15 @@ struct Ctx {
     const void* W64;
     const void* Wlo;
     int Wlo_prec;
+    const ok_net* net;   // the preconditioner of the current solve, or NULL
     hipStream_t st;
     Work w;
     int tps64, tpslo;
 };
+
+int apply_net(Ctx& C, const float* in, float* out, int nf, bool inner, void* work) {
+    return net_apply(C.g, C.net->n_layers, C.net->d_params, C.net->d_T, in, out, nf, inner, work, C.st);
+}
 
 int read_scal(Ctx& C, Scal* h) {
     OK_HIP(hipMemcpyAsync(h, C.w.sc, sizeof(Scal), hipMemcpyDeviceToHost, C.st));
@@ -117,16 +135,25 @@ int source_norm(Ctx& C, const double* xi, double* xn) {
 }
 
 // One BiCGStab iteration on fields of type T (f64 selects double) with operator (W, prec, tps).
+// With C.net (FP32 fields only) p^ and s^ are C.w.f32[7] and [8].
 int iterate(Ctx& C, bool f64, const void* W, int prec, int tps, void* x, void* r, void* rhat, void* p, void* v,
             void* s, void* t) {
     const Geo& g = C.g;
+    void* ph = p;
+    void* sh = s;
+    if (C.net) {
+        ph = C.w.f32[7];
+        sh = C.w.f32[8];
+    }
     OK_TRY(launch_p_update(g, f64, p, r, v, C.w.sc, C.st));
-    OK_TRY(launch_apply(g, W, prec, p, v, C.c->mhat, tps, EPI_RV, rhat, C.w.partial, C.st));
+    if (C.net) OK_TRY(apply_net(C, static_cast<float*>(p), static_cast<float*>(ph), 1, false, C.w.netw));
+    OK_TRY(launch_apply(g, W, prec, ph, v, C.c->mhat, tps, EPI_RV, rhat, C.w.partial, C.st));
     OK_TRY(fin(C, FIN_ALPHA, apply_blocks(g, tps)));
     OK_TRY(launch_s_update(g, f64, s, r, v, C.w.sc, C.st));
-    OK_TRY(launch_apply(g, W, prec, s, t, C.c->mhat, tps, EPI_TS, nullptr, C.w.partial, C.st));
+    if (C.net) OK_TRY(apply_net(C, static_cast<float*>(s), static_cast<float*>(sh), 1, false, C.w.netw));
+    OK_TRY(launch_apply(g, W, prec, sh, t, C.c->mhat, tps, EPI_TS, nullptr, C.w.partial, C.st));
     OK_TRY(fin(C, FIN_OMEGA, apply_blocks(g, tps)));
-    OK_TRY(launch_xr_update(g, f64, x, r, p, s, t, rhat, C.w.sc, C.w.partial, C.st));
+    OK_TRY(launch_xr_update(g, f64, x, r, ph, sh, s, t, rhat, C.w.sc, C.w.partial, C.st));
     OK_TRY(fin_blas(C, FIN_RHO));
     return OK_SUCCESS;
 }
@@ -236,6 +263,8 @@ int solve_mixed(Ctx& C, const double* xi, double* x64, ok_solver_stats* S) {
     OK_TRY(launch_zero(C.g, false, xlo, C.st));
     OK_TRY(restart_from(C, false, r, rhat, p, v));
     double maxr = std::sqrt(rr);
+    double best = maxr;
+    int best_it = S->iterations;
     Scal h;
     while (true) {
         if (S->iterations >= P.max_iter) {
@@ -246,15 +275,31 @@ int solve_mixed(Ctx& C, const double* xi, double* x64, ok_solver_stats* S) {
         }
         OK_TRY(iterate(C, false, C.Wlo, C.Wlo_prec, C.tpslo, xlo, r, rhat, p, v, s, t));
         S->matvec_lo += 2;
+        if (C.net) S->net_applies += 2;
         S->iterations++;
         OK_TRY(read_scal(C, &h));
         const double rn = std::sqrt(h.rr);
         if (P.verbose) fprintf(stderr, "okinv bicgstab32 it %d |r|/|xi| %.3e\n", S->iterations, rn / xn);
+        const bool broke = h.flags & 1;
+        if (C.net) {
+            // the network's recurrence failed: x64 holds the last reliable iterate
+            if (rn < best) {
+                best = rn;
+                best_it = S->iterations;
+            }
+            const bool stalled = P.stall_window > 0 && S->iterations - best_it >= P.stall_window;
+            if (!std::isfinite(rn) || broke || stalled) {
+                if (P.verbose) fprintf(stderr, "okinv preconditioned solve %s at iteration %d: fallback\n",
+                                       !std::isfinite(rn) ? "non-finite" : broke ? "broke down" : "stalled",
+                                       S->iterations);
+                if (std::isfinite(rn)) OK_TRY(launch_accum_x(C.g, x64, xlo, C.st));
+                return kFallback;
+            }
+        }
         if (!std::isfinite(rn)) {
             set_error("low-precision residual became non-finite at iteration %d", S->iterations);
             return S->status = OK_ENONFINITE;
         }
-        const bool broke = h.flags & 1;
         maxr = std::max(maxr, rn);
         if (rn < P.delta * maxr || rn / xn <= P.tol || broke) {
             // reliable update: fold x32 into x64 and recompute the residual in FP64
@@ -289,10 +334,11 @@ struct WorkB {
     ScalB* sc;
     double2* partial;
     double* t64;
-    float* f[7];   // x32 r rhat p v s t
+    float* f[9];   // x32 r rhat p v s t ; with a network also p^ s^
+    void* netw;
 };
 
-size_t layout_batched(const Geo& g, int nrhs, char* base, WorkB* w) {
+size_t layout_batched(const Geo& g, int nrhs, int net_layers, char* base, WorkB* w) {
     size_t off = 0;
     auto take = [&](size_t n) {
         char* p = base ? base + off : nullptr;
@@ -305,7 +351,8 @@ size_t layout_batched(const Geo& g, int nrhs, char* base, WorkB* w) {
     const int nb = std::max(kGridB, col_blocks(g));
     W.partial = reinterpret_cast<double2*>(take((size_t)nb * kMaxRhsB * 2 * sizeof(double2)));
     W.t64 = reinterpret_cast<double*>(take((size_t)g.V * 12 * 16));
-    for (int i = 0; i < 7; ++i) W.f[i] = reinterpret_cast<float*>(take((size_t)g.V * 12 * nrhs * 8));
+    for (int i = 0; i < (net_layers ? 9 : 7); ++i) W.f[i] = reinterpret_cast<float*>(take((size_t)g.V * 12 * nrhs * 8));
+    W.netw = net_layers ? take(net_apply_work_bytes(g, net_layers, nrhs)) : nullptr;
     return off;
 }
 
@@ -347,8 +394,10 @@ int batched_restart(Ctx& C, WorkB& B, int nrhs, int j) {
     return bfin(C, B, FIN_INIT, col_blocks(g), j, 1);
 }
 
-// xi, x: FP64 [nrhs][V][12]; S: nrhs stats.  Returns the first failing status.
-int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_solver_stats* S) {
+// xi, x: FP64 [nrhs][V][12]; S: nrhs stats.  Returns the first failing status.  With
+// C.net, right-hand sides whose preconditioned recurrence fails get fallback[j] = 1
+// (x64 holds their last reliable iterate) and take no part in the returned status.
+int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_solver_stats* S, int* fallback) {
     const ok_solver_params& P = *C.p;
     const Geo& g = C.g;
     const size_t fb = (size_t)g.V * 12 * nrhs * 8;
@@ -362,7 +411,8 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
     OK_HIP(hipMemsetAsync(rhat, 0, fb, C.st));
     ScalB h;
     memset(&h, 0, sizeof(h));
-    double xn[kMaxRhsB], maxr[kMaxRhsB];
+    double xn[kMaxRhsB], maxr[kMaxRhsB], best[kMaxRhsB];
+    int best_it[kMaxRhsB];
     int rc_all = OK_SUCCESS;
     for (int j = 0; j < nrhs; ++j) {
         OK_TRY(launch_col_norm64(g, j, xi + j * col, B.partial, C.st));
@@ -397,7 +447,8 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
         h.active[j] = 1;
         OK_HIP(hipMemcpyAsync(&B.sc->active[j], &h.active[j], sizeof(int), hipMemcpyHostToDevice, C.st));
         OK_TRY(batched_restart(C, B, nrhs, j));
-        maxr[j] = std::sqrt(rr);
+        maxr[j] = best[j] = std::sqrt(rr);
+        best_it[j] = 0;
     }
     OK_TRY(write_active(C, B, &h));
     auto any_active = [&]() {
@@ -420,15 +471,19 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
             }
             break;
         }
+        float* ph = C.net ? B.f[7] : p;
+        float* sh = C.net ? B.f[8] : s;
         OK_TRY(launch_bp_update(g, nrhs, p, r, v, B.sc, C.st));
-        OK_TRY(launch_apply_site(g, C.Wlo, wp, p, v, C.c->mhat, nrhs, 1, C.st));
+        if (C.net) OK_TRY(apply_net(C, p, ph, nrhs, true, B.netw));
+        OK_TRY(launch_apply_site(g, C.Wlo, wp, ph, v, C.c->mhat, nrhs, 1, C.st));
         OK_TRY(launch_bdot(g, nrhs, rhat, v, B.sc, B.partial, C.st));
         OK_TRY(bfin(C, B, FIN_ALPHA, kGridB, 0, nrhs));
         OK_TRY(launch_bs_update(g, nrhs, s, r, v, B.sc, C.st));
-        OK_TRY(launch_apply_site(g, C.Wlo, wp, s, t, C.c->mhat, nrhs, 1, C.st));
+        if (C.net) OK_TRY(apply_net(C, s, sh, nrhs, true, B.netw));
+        OK_TRY(launch_apply_site(g, C.Wlo, wp, sh, t, C.c->mhat, nrhs, 1, C.st));
         OK_TRY(launch_bdot(g, nrhs, t, s, B.sc, B.partial, C.st));
         OK_TRY(bfin(C, B, FIN_OMEGA, kGridB, 0, nrhs));
-        OK_TRY(launch_bxr_update(g, nrhs, x32, r, p, s, t, rhat, B.sc, B.partial, C.st));
+        OK_TRY(launch_bxr_update(g, nrhs, x32, r, ph, sh, s, t, rhat, B.sc, B.partial, C.st));
         OK_TRY(bfin(C, B, FIN_RHO, kGridB, 0, nrhs));
         ScalB hd;
         OK_TRY(read_scalb(C, B, &hd));
@@ -438,8 +493,24 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
             if (!h.active[j]) continue;
             S[j].iterations++;
             S[j].matvec_lo += 2;
+            if (C.net) S[j].net_applies += 2;
             const double rn = std::sqrt(hd.rr[j]);
             if (P.verbose) fprintf(stderr, "okinv batched it %d rhs %d |r|/|xi| %.3e\n", it, j, rn / xn[j]);
+            if (C.net) {
+                if (rn < best[j]) {
+                    best[j] = rn;
+                    best_it[j] = it;
+                }
+                const bool stalled = P.stall_window > 0 && it - best_it[j] >= P.stall_window;
+                if (!std::isfinite(rn) || (hd.flags[j] & 1) || stalled) {
+                    if (P.verbose) fprintf(stderr, "okinv batched rhs %d: preconditioned solve failed at %d\n", j, it);
+                    if (std::isfinite(rn)) OK_TRY(launch_col_accum(g, nrhs, j, x + j * col, x32, C.st));
+                    fallback[j] = 1;
+                    h.active[j] = 0;
+                    changed = true;
+                    continue;
+                }
+            }
             if (!std::isfinite(rn)) {
                 set_error("residual of right-hand side %d became non-finite at iteration %d", j, it);
                 S[j].status = OK_ENONFINITE;
@@ -487,7 +558,31 @@ using namespace okinv;
 
 extern "C" {
 
-int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t* bytes) {
+namespace {
+
+int check_solver_net(const ok_net* net, bool mixed) {
+    if (!net) return OK_SUCCESS;
+    if (!mixed) {
+        set_error("the preconditioner network needs the low-precision solve (d_Wlo)");
+        return OK_EINVAL;
+    }
+    if (net->n_layers < 1 || net->n_layers > OK_NET_MAX_LAYERS) {
+        set_error("net->n_layers = %d outside [1, %d]", net->n_layers, OK_NET_MAX_LAYERS);
+        return OK_EINVAL;
+    }
+    int rc = check_ptr(net->d_params, "net->d_params");
+    return rc ? rc : check_ptr(net->d_T, "net->d_T");
+}
+
+size_t workspace(const Geo& G, int nrhs, int Wlo_prec, const ok_net* net) {
+    const int nl = net ? net->n_layers : 0;
+    if (Wlo_prec >= 0 && (Wlo_prec & OK_LAYOUT_SITE)) return layout_batched(G, std::min(nrhs, kMaxRhsB), nl, nullptr, nullptr);
+    return layout(G, Wlo_prec >= 0, nl, nullptr, nullptr);
+}
+
+}  // namespace
+
+int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const ok_net* net, size_t* bytes) {
     Geo G;
     int rc = make_geo(g, &G);
     if (rc) return rc;
@@ -500,17 +595,14 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, size_t
         set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE), or negative (plain FP64)");
         return OK_EINVAL;
     }
-    if (Wlo_prec >= 0 && (Wlo_prec & OK_LAYOUT_SITE))
-        *bytes = layout_batched(G, std::min(nrhs, kMaxRhsB), nullptr, nullptr);
-    else
-        *bytes = layout(G, Wlo_prec >= 0, nullptr, nullptr);
+    if ((rc = check_solver_net(net, Wlo_prec >= 0))) return rc;
+    *bytes = workspace(G, nrhs, Wlo_prec, net);
     return OK_SUCCESS;
 }
 
 int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p, const void* d_W64,
-                const void* d_Wlo, int Wlo_prec, const double* d_xi, double* d_psi, int nrhs, void* d_work,
-                size_t work_bytes, ok_solver_stats* stats, void* stream) {
-    const auto t0 = std::chrono::steady_clock::now();
+                const void* d_Wlo, int Wlo_prec, const ok_net* net, const double* d_xi, double* d_psi, int nrhs,
+                void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream) {
     Ctx C;
     int rc = make_geo(g, &C.g);
     if (rc) return rc;
@@ -522,8 +614,9 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
         set_error("invalid coefficients");
         return OK_EINVAL;
     }
-    if (!(p->tol > 0) || p->max_iter < 0 || p->max_restarts < 0 || !(p->delta > 0 && p->delta < 1)) {
-        set_error("invalid solver parameters (tol > 0, max_iter >= 0, 0 < delta < 1)");
+    if (!(p->tol > 0) || p->max_iter < 0 || p->max_restarts < 0 || !(p->delta > 0 && p->delta < 1) ||
+        p->stall_window < 0) {
+        set_error("invalid solver parameters (tol > 0, max_iter >= 0, 0 < delta < 1, stall_window >= 0)");
         return OK_EINVAL;
     }
     if (nrhs < 1 || nrhs > 4096) {
@@ -536,12 +629,12 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
         set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE) when d_Wlo is given");
         return OK_EINVAL;
     }
+    if ((rc = check_solver_net(net, mixed))) return rc;
     const bool batched = mixed && (Wlo_prec & OK_LAYOUT_SITE);
     if ((rc = check_ptr(d_W64, "d_W64")) || (mixed && (rc = check_ptr(d_Wlo, "d_Wlo"))) ||
         (rc = check_ptr(d_xi, "d_xi")) || (rc = check_ptr(d_psi, "d_psi")) || (rc = check_ptr(d_work, "d_work")))
         return rc;
-    const size_t need = batched ? layout_batched(C.g, std::min(nrhs, kMaxRhsB), nullptr, nullptr)
-                                : layout(C.g, mixed, nullptr, nullptr);
+    const size_t need = workspace(C.g, nrhs, mixed ? Wlo_prec : -1, net);
     if (work_bytes < need) {
         set_error("workspace has %zu bytes, needs %zu", work_bytes, need);
         return OK_ESIZE;
@@ -554,19 +647,24 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
             return OK_EINVAL;
         }
     }
+    const int nl = net ? net->n_layers : 0;
     WorkB B;
     if (batched)
-        layout_batched(C.g, std::min(nrhs, kMaxRhsB), reinterpret_cast<char*>(d_work), &B);
+        layout_batched(C.g, std::min(nrhs, kMaxRhsB), nl, reinterpret_cast<char*>(d_work), &B);
     else
-        layout(C.g, mixed, reinterpret_cast<char*>(d_work), &C.w);
+        layout(C.g, mixed, nl, reinterpret_cast<char*>(d_work), &C.w);
     C.c = c;
     C.p = p;
     C.W64 = d_W64;
     C.Wlo = d_Wlo;
     C.Wlo_prec = Wlo_prec;
+    C.net = net;
     C.st = reinterpret_cast<hipStream_t>(stream);
     C.tps64 = stencil_tps(OK_F64);
     C.tpslo = mixed ? stencil_tps(wlb) : 1;
+    // the fallback continues from the iterate in d_psi
+    ok_solver_params pf = *p;
+    pf.zero_guess = 0;
     int first_bad = OK_SUCCESS;
     if (batched) {
         for (int k0 = 0; k0 < nrhs; k0 += kMaxRhsB) {
@@ -574,11 +672,25 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
             const auto tk = std::chrono::steady_clock::now();
             for (int k = 0; k < nk; ++k) stats[k0 + k] = ok_solver_stats{};
             const size_t off = (size_t)k0 * C.g.V * 24;
-            rc = solve_batched(C, B, nk, d_xi + off, d_psi + off, stats + k0);
-            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - tk).count();
-            for (int k = 0; k < nk; ++k) stats[k0 + k].seconds = sec;
+            int fb[kMaxRhsB] = {0};
+            C.net = net;
+            C.p = p;
+            rc = solve_batched(C, B, nk, d_xi + off, d_psi + off, stats + k0, fb);
             if (rc < 0) return rc;
             if (rc != OK_SUCCESS && first_bad == OK_SUCCESS) first_bad = rc;
+            C.net = nullptr;
+            C.p = &pf;
+            for (int k = 0; k < nk; ++k) {
+                if (!fb[k]) continue;
+                const size_t o1 = (size_t)(k0 + k) * C.g.V * 24;
+                stats[k0 + k].fallbacks = 1;
+                int dummy = 0;
+                rc = solve_batched(C, B, 1, d_xi + o1, d_psi + o1, stats + k0 + k, &dummy);
+                if (rc < 0) return rc;
+                if (rc != OK_SUCCESS && first_bad == OK_SUCCESS) first_bad = rc;
+            }
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - tk).count();
+            for (int k = 0; k < nk; ++k) stats[k0 + k].seconds = sec;
         }
         return first_bad;
     }
@@ -587,7 +699,15 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
         ok_solver_stats& S = stats[k];
         S = ok_solver_stats{};
         const size_t off = (size_t)k * C.g.V * 24;
+        C.net = net;
+        C.p = p;
         rc = mixed ? solve_mixed(C, d_xi + off, d_psi + off, &S) : solve_plain(C, d_xi + off, d_psi + off, &S);
+        if (rc == kFallback) {
+            S.fallbacks = 1;
+            C.net = nullptr;
+            C.p = &pf;
+            rc = solve_mixed(C, d_xi + off, d_psi + off, &S);
+        }
         S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tk).count();
         if (rc < 0) {
             S.status = rc;
@@ -595,7 +715,6 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
         }
         if (rc != OK_SUCCESS && first_bad == OK_SUCCESS) first_bad = rc;
     }
-    (void)t0;
     return first_bad;
 }
 

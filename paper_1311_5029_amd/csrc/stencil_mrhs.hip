@@ -47,15 +47,6 @@ template <> struct MR<OK_BF16> {
     static constexpr int CHP = 37;
 };
 
-// The hardware places workgroup b on XCD b % 8.  Hand each XCD a contiguous
-// range of tiles so that neighbouring sites are served by the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-    const int x = b & 7, q = b >> 3;
-    int start = 0;
-    for (int y = 0; y < x; ++y) start += (n - y + 7) >> 3;
-    return start + q;
-}
-
 template <int P>
 __global__ void __launch_bounds__(BS, 2) k_apply_mrhs(Geo g, const uint4* __restrict__ W,
                                                       const float* __restrict__ psi, float* __restrict__ out,

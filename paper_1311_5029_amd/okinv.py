@@ -23,6 +23,8 @@ _lib = C.CDLL(LIB_PATH)
 OK_F64, OK_F32, OK_BF16 = 0, 1, 2
 OK_LAYOUT_SITE = 0x10
 OK_SPINOR_RHS_INNER = 0x20
+OK_NET_ADJOINT = 0x40
+OK_NET_MAX_LAYERS = 16
 OK_SUCCESS, OK_NOT_CONVERGED, OK_BREAKDOWN = 0, 1, 2
 OK_EINVAL, OK_ESIZE, OK_EALIGN, OK_EDEVICE, OK_ENONFINITE = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK_SUCCESS", 1: "OK_NOT_CONVERGED", 2: "OK_BREAKDOWN", -1: "OK_EINVAL",
@@ -40,19 +42,30 @@ class ok_coeffs(C.Structure):
 
 class ok_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("delta", C.c_double), ("max_iter", C.c_int32),
-                ("max_restarts", C.c_int32), ("zero_guess", C.c_int32), ("verbose", C.c_int32)]
+                ("max_restarts", C.c_int32), ("zero_guess", C.c_int32), ("verbose", C.c_int32),
+                ("stall_window", C.c_int32)]
 
 
 class ok_solver_stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("matvec_hi", C.c_int32),
                 ("matvec_lo", C.c_int32), ("reliable_updates", C.c_int32), ("restarts", C.c_int32),
+                ("net_applies", C.c_int32), ("fallbacks", C.c_int32),
                 ("true_rel_resid", C.c_double), ("seconds", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class ok_net(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("reserved", C.c_int32), ("d_params", C.c_void_p), ("d_T", C.c_void_p)]
+
+
+class ok_adam_cfg(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 _P = C.c_void_p
+_NET = C.POINTER(ok_net)
 _sig = {
     "ok_abi_version": ([], C.c_int),
     "ok_last_error": ([], C.c_char_p),
@@ -63,9 +76,22 @@ _sig = {
     "ok_apply_M": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), _P, C.c_int, _P, _P, C.c_int, C.c_int, _P],
                    C.c_int),
     "ok_W_to_dense": ([C.POINTER(ok_geom), _P, C.c_int, _P, _P], C.c_int),
-    "ok_bicgstab_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
-    "ok_bicgstab": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, C.c_int,
+    "ok_bicgstab_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.c_int, _NET, C.POINTER(C.c_size_t)], C.c_int),
+    "ok_bicgstab": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, C.c_int, _NET,
                      _P, _P, C.c_int, _P, C.c_size_t, C.POINTER(ok_solver_stats), _P], C.c_int),
+    "ok_net_param_count": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "ok_net_transports_bytes": ([C.POINTER(ok_geom), C.POINTER(C.c_size_t)], C.c_int),
+    "ok_net_transports": ([C.POINTER(ok_geom), _P, _P, C.c_size_t, _P], C.c_int),
+    "ok_net_layer": ([C.POINTER(ok_geom), _P, _P, _P, _P, C.c_int, C.c_int, _P], C.c_int),
+    "ok_net_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "ok_net_apply": ([C.POINTER(ok_geom), _NET, _P, _P, C.c_int, C.c_int, _P, C.c_size_t, _P], C.c_int),
+    "ok_net_layer_wgrad": ([C.POINTER(ok_geom), _P, _P, _P, _P, C.c_int, C.c_int, _P, C.c_size_t, _P], C.c_int),
+    "ok_net_loss_grad": ([C.POINTER(ok_geom), _P, _P, _P, _P, C.c_int, C.c_int, _P, C.c_size_t, _P], C.c_int),
+    "ok_net_loss_and_grad": ([C.POINTER(ok_geom), _NET, _P, _P, C.c_int, C.c_int, _P, _P, _P, C.c_size_t, _P],
+                             C.c_int),
+    "ok_adam_step": ([_P, _P, _P, _P, C.c_size_t, C.POINTER(ok_adam_cfg), C.c_int, _P], C.c_int),
+    "ok_net_train_step": ([C.POINTER(ok_geom), C.c_int, _P, _P, _P, _P, _P, _P, C.c_int, C.c_int,
+                           C.POINTER(ok_adam_cfg), C.c_int, _P, _P, _P, C.c_size_t, _P], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -156,9 +182,9 @@ def ok_W_to_dense(dims, d_W, prec, d_dense, stream=None):
     return _check(_lib.ok_W_to_dense(C.byref(geom(dims)), _ptr(d_W), prec, _ptr(d_dense), _stream(stream)))
 
 
-def ok_bicgstab_workspace_bytes(dims, nrhs, Wlo_prec=-1):
+def ok_bicgstab_workspace_bytes(dims, nrhs, Wlo_prec=-1, net=None):
     n = C.c_size_t()
-    _check(_lib.ok_bicgstab_workspace_bytes(C.byref(geom(dims)), nrhs, Wlo_prec, C.byref(n)))
+    _check(_lib.ok_bicgstab_workspace_bytes(C.byref(geom(dims)), nrhs, Wlo_prec, _netp(net), C.byref(n)))
     return n.value
 
 
@@ -170,21 +196,108 @@ class SolverParams:
     max_restarts: int = 5
     zero_guess: int = 1
     verbose: int = 0
+    stall_window: int = 0
 
     def c(self):
         return ok_solver_params(self.tol, self.delta, self.max_iter, self.max_restarts,
-                                self.zero_guess, self.verbose)
+                                self.zero_guess, self.verbose, self.stall_window)
 
 
-def ok_bicgstab(dims, c, params, d_W64, d_Wlo, Wlo_prec, d_xi, d_psi, nrhs, d_work, stream=None):
-    """Returns (status, [stats dict per right-hand side])."""
+def ok_bicgstab(dims, c, params, d_W64, d_Wlo, Wlo_prec, d_xi, d_psi, nrhs, d_work, stream=None, net=None):
+    """Returns (status, [stats dict per right-hand side]).  net: Net or None."""
     stats = (ok_solver_stats * nrhs)()
     p = params.c() if isinstance(params, SolverParams) else params
     rc = _lib.ok_bicgstab(C.byref(geom(dims)), C.byref(coeffs(c)), C.byref(p), _ptr(d_W64), _ptr(d_Wlo),
-                          Wlo_prec, _ptr(d_xi), _ptr(d_psi), nrhs, _ptr(d_work), _nbytes(d_work), stats,
-                          _stream(stream))
+                          Wlo_prec, _netp(net), _ptr(d_xi), _ptr(d_psi), nrhs, _ptr(d_work), _nbytes(d_work),
+                          stats, _stream(stream))
     _check(rc)
     return rc, [s.as_dict() for s in stats]
+
+
+# --------------------------------------------------------------------------- learned preconditioner
+@dataclasses.dataclass
+class Net:
+    """n_layers and the device tensors of its parameters and transports (kept alive by this object)."""
+    n_layers: int
+    params: object
+    T: object
+
+    def c(self):
+        return ok_net(self.n_layers, 0, _ptr(self.params), _ptr(self.T))
+
+
+def _netp(net):
+    if net is None:
+        return None
+    n = net.c() if isinstance(net, Net) else net
+    return C.pointer(n)
+
+
+def ok_net_param_count(n_layers):
+    n = C.c_size_t()
+    _check(_lib.ok_net_param_count(n_layers, C.byref(n)))
+    return n.value
+
+
+def ok_net_transports_bytes(dims):
+    n = C.c_size_t()
+    _check(_lib.ok_net_transports_bytes(C.byref(geom(dims)), C.byref(n)))
+    return n.value
+
+
+def ok_net_transports(dims, d_links, d_T, stream=None):
+    return _check(_lib.ok_net_transports(C.byref(geom(dims)), _ptr(d_links), _ptr(d_T), _nbytes(d_T),
+                                         _stream(stream)))
+
+
+def ok_net_layer(dims, d_A, d_T, d_in, d_out, nfields, flags=0, stream=None):
+    return _check(_lib.ok_net_layer(C.byref(geom(dims)), _ptr(d_A), _ptr(d_T), _ptr(d_in), _ptr(d_out), nfields,
+                                    flags, _stream(stream)))
+
+
+def ok_net_workspace_bytes(dims, n_layers, nfields, training):
+    n = C.c_size_t()
+    _check(_lib.ok_net_workspace_bytes(C.byref(geom(dims)), n_layers, nfields, training, C.byref(n)))
+    return n.value
+
+
+def ok_net_apply(dims, net, d_in, d_out, nfields, flags, d_work, stream=None):
+    return _check(_lib.ok_net_apply(C.byref(geom(dims)), _netp(net), _ptr(d_in), _ptr(d_out), nfields, flags,
+                                    _ptr(d_work), _nbytes(d_work) if d_work is not None else 0, _stream(stream)))
+
+
+def ok_net_layer_wgrad(dims, d_T, d_gout, d_in, d_gA, nfields, flags, d_work, stream=None):
+    return _check(_lib.ok_net_layer_wgrad(C.byref(geom(dims)), _ptr(d_T), _ptr(d_gout), _ptr(d_in), _ptr(d_gA),
+                                          nfields, flags, _ptr(d_work), _nbytes(d_work), _stream(stream)))
+
+
+def ok_net_loss_grad(dims, d_out, d_psi, d_gout, d_loss, nfields, flags, d_work, stream=None):
+    return _check(_lib.ok_net_loss_grad(C.byref(geom(dims)), _ptr(d_out), _ptr(d_psi), _ptr(d_gout),
+                                        _ptr(d_loss), nfields, flags, _ptr(d_work), _nbytes(d_work),
+                                        _stream(stream)))
+
+
+def ok_net_loss_and_grad(dims, net, d_xi, d_psi, nfields, flags, d_loss, d_grad, d_work, stream=None):
+    return _check(_lib.ok_net_loss_and_grad(C.byref(geom(dims)), _netp(net), _ptr(d_xi), _ptr(d_psi), nfields,
+                                            flags, _ptr(d_loss), _ptr(d_grad), _ptr(d_work), _nbytes(d_work),
+                                            _stream(stream)))
+
+
+def adam_cfg(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    return ok_adam_cfg(lr, beta1, beta2, eps)
+
+
+def ok_adam_step(d_p, d_g, d_m, d_v, n, cfg, step, stream=None):
+    return _check(_lib.ok_adam_step(_ptr(d_p), _ptr(d_g), _ptr(d_m), _ptr(d_v), n, C.byref(cfg), step,
+                                    _stream(stream)))
+
+
+def ok_net_train_step(dims, n_layers, d_params, d_m, d_v, d_T, d_xi, d_psi, nfields, flags, cfg, step, d_loss,
+                      d_grad, d_work, stream=None):
+    return _check(_lib.ok_net_train_step(C.byref(geom(dims)), n_layers, _ptr(d_params), _ptr(d_m), _ptr(d_v),
+                                         _ptr(d_T), _ptr(d_xi), _ptr(d_psi), nfields, flags, C.byref(cfg), step,
+                                         _ptr(d_loss), _ptr(d_grad), _ptr(d_work), _nbytes(d_work),
+                                         _stream(stream)))
 
 
 # --------------------------------------------------------------------------- plumbing

@@ -37,7 +37,7 @@ def test_binding_covers_header():
 
 def test_abi_version():
     from paper_1311_5029_amd import okinv
-    assert okinv.ok_abi_version() == 1
+    assert okinv.ok_abi_version() == 2
 
 
 def test_size_queries():
@@ -128,8 +128,8 @@ def test_solver_validation_before_device():
     stats = (okinv.ok_solver_stats * 1)()
     need = okinv.ok_bicgstab_workspace_bytes(dims, 1)
     good = okinv.SolverParams().c()
-    args = lambda p, work, wlo=None, wlo_prec=-1: (
-        ctypes.byref(g), ctypes.byref(c), ctypes.byref(p), 0x10000000, wlo, wlo_prec, 0x20000000, 0x30000000, 1,
+    args = lambda p, work, wlo=None, wlo_prec=-1, net=None: (
+        ctypes.byref(g), ctypes.byref(c), ctypes.byref(p), 0x10000000, wlo, wlo_prec, net, 0x20000000, 0x30000000, 1,
         0x40000000, work, stats, None)
     assert lib.ok_bicgstab(*args(good, need - 256)) == okinv.OK_ESIZE
     bad = okinv.SolverParams(tol=-1.0).c()
@@ -139,6 +139,66 @@ def test_solver_validation_before_device():
     # low-precision W given with an FP64 precision tag
     need2 = okinv.ok_bicgstab_workspace_bytes(dims, 1, okinv.OK_F32)
     assert lib.ok_bicgstab(*args(good, need2, 0x50000000, okinv.OK_F64)) == okinv.OK_EINVAL
+    # a network needs the low-precision solve, a valid depth and room for its fields
+    net = okinv.ok_net(4, 0, 0x60000000, 0x70000000)
+    with pytest.raises(okinv.OkError):
+        okinv.ok_bicgstab_workspace_bytes(dims, 1, -1, net)
+    assert lib.ok_bicgstab(*args(good, need, None, -1, ctypes.byref(net))) == okinv.OK_EINVAL
+    need3 = okinv.ok_bicgstab_workspace_bytes(dims, 1, okinv.OK_F32, net)
+    assert need3 >= need2 + 4 * 256 * 96
+    assert lib.ok_bicgstab(*args(good, need3 - 256, 0x50000000, okinv.OK_F32, ctypes.byref(net))) == okinv.OK_ESIZE
+    bad_net = okinv.ok_net(0, 0, 0x60000000, 0x70000000)
+    assert lib.ok_bicgstab(*args(good, need3, 0x50000000, okinv.OK_F32, ctypes.byref(bad_net))) == okinv.OK_EINVAL
+    bad = okinv.SolverParams(stall_window=-1).c()
+    assert lib.ok_bicgstab(*args(bad, need2, 0x50000000, okinv.OK_F32)) == okinv.OK_EINVAL
+
+
+def test_net_sizes_and_validation_before_device():
+    from paper_1311_5029_amd import okinv
+    dims = (4, 5, 6, 7)
+    V = 4 * 5 * 6 * 7
+    Vs = (V + 63) // 64 * 64
+    assert okinv.ok_net_param_count(4) == 4 * 27 * 16 * 2
+    assert okinv.ok_net_transports_bytes(dims) == 13 * 9 * 8 * Vs
+    fb = V * 12 * 8
+    # apply: ping-pong fields for deep networks, none for one layer
+    assert okinv.ok_net_workspace_bytes(dims, 1, 3, 0) == 256
+    assert okinv.ok_net_workspace_bytes(dims, 4, 3, 0) >= 2 * 3 * fb
+    # training keeps every layer's output
+    assert okinv.ok_net_workspace_bytes(dims, 4, 3, 1) >= 4 * 3 * fb
+    for bad in [(0, 1, 0), (17, 1, 0), (4, 0, 0), (4, 1, 3)]:
+        with pytest.raises(okinv.OkError) as e:
+            okinv.ok_net_workspace_bytes(dims, *bad)
+        assert e.value.status == okinv.OK_EINVAL
+    with pytest.raises(okinv.OkError):
+        okinv.ok_net_param_count(0)
+    g = okinv.geom(dims)
+    lib = okinv._lib
+    # transports buffer too small
+    need = okinv.ok_net_transports_bytes(dims)
+    assert lib.ok_net_transports(ctypes.byref(g), 0x10000000, 0x20000000, need - 8, None) == okinv.OK_ESIZE
+    # layer: overlapping fields, unknown flag, misaligned pointer
+    assert lib.ok_net_layer(ctypes.byref(g), 0x10000000, 0x20000000, 0x30000000, 0x30000000 + 64, 1, 0,
+                            None) == okinv.OK_EINVAL
+    assert lib.ok_net_layer(ctypes.byref(g), 0x10000000, 0x20000000, 0x30000000, 0x40000000, 1, 0x80,
+                            None) == okinv.OK_EINVAL
+    assert lib.ok_net_layer(ctypes.byref(g), 0x10000008, 0x20000000, 0x30000000, 0x40000000, 1, 0,
+                            None) == okinv.OK_EALIGN
+    # training step: workspace too small, missing loss pointer
+    wt = okinv.ok_net_workspace_bytes(dims, 2, 2, 1)
+    cfg = okinv.adam_cfg()
+    base = [ctypes.byref(g), 2, 0x10000000, 0x11000000, 0x12000000, 0x13000000, 0x20000000, 0x30000000, 2, 0,
+            ctypes.byref(cfg), 1, 0x14000000, 0x15000000, 0x40000000]
+    assert lib.ok_net_train_step(*base, wt - 256, None) == okinv.OK_ESIZE
+    nol = list(base)
+    nol[12] = None
+    assert lib.ok_net_train_step(*nol, wt, None) == okinv.OK_EINVAL
+    # Adam settings
+    badcfg = okinv.adam_cfg(beta1=1.0)
+    assert lib.ok_adam_step(0x10000000, 0x11000000, 0x12000000, 0x13000000, 10, ctypes.byref(badcfg), 1,
+                            None) == okinv.OK_EINVAL
+    assert lib.ok_adam_step(0x10000000, 0x11000000, 0x12000000, 0x13000000, 10, ctypes.byref(cfg), 0,
+                            None) == okinv.OK_EINVAL
 
 
 def test_host_complex_roundtrip():

@@ -23,20 +23,20 @@ TOL = 1e-10
 ORACLE_SLACK = 1.05
 
 
-def solve(L, xi, low=None, params=None, guess=None):
+def solve(L, xi, low=None, params=None, guess=None, net=None):
     ok = L.ok
     torch = L.torch
     nrhs = xi.shape[0] if xi.ndim == 7 else 1
     d_xi = ok.to_device_complex(xi)
     psi = ok.to_device_complex(guess) if guess is not None else torch.zeros_like(d_xi)
     lo_prec = -1 if low is None else low
-    work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(L.dims, nrhs, lo_prec))
+    work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(L.dims, nrhs, lo_prec, net))
     W64 = L.precompute(ok.OK_F64)
     Wlo = None if low is None else L.precompute(low)
     p = params or ok.SolverParams(tol=TOL)
     if guess is not None:
         p.zero_guess = 0
-    rc, st = ok.ok_bicgstab(L.dims, L.c, p, W64, Wlo, lo_prec, d_xi, psi, nrhs, work)
+    rc, st = ok.ok_bicgstab(L.dims, L.c, p, W64, Wlo, lo_prec, d_xi, psi, nrhs, work, net=net)
     torch.cuda.synchronize()
     return rc, st, ok.to_host_complex(psi, xi.shape)
 
@@ -232,3 +232,78 @@ def test_batched_plaquette06_point_sources():
     assert rc == ok.OK_SUCCESS
     for k in (0, 4, 11):
         assert oracle_resid(cfg["U"], cfg["coeffs"], xi[k], x[k]) <= ORACLE_SLACK * TOL
+
+
+# --- right preconditioning by the learned network ---------------------------------------------
+@pytest.fixture(scope="module")
+def c4small():
+    """The C4 link ensemble at 8^3 x 8, with a network trained on 16 GPU-solved pairs."""
+    from gpu_util import train_net
+    ok = lib()
+    dims = (8, 8, 8, 8)
+    cfg = I.make_config("C4", dims=dims)
+    L = Lattice(dims, cfg["U"], cfg["coeffs"])
+    xi = I.gaussian_sources(dims, 16, I.SEED_TRAIN)
+    rc, st, psi = solve(L, xi, low=ok.OK_BF16 | SITE)
+    assert rc == ok.OK_SUCCESS
+    L.net, L.loss = train_net(L, xi, psi, steps=300)
+    L.cfg = cfg
+    L.xi_eval = I.gaussian_sources(dims, 4, I.SEED_EVAL)
+    return L
+
+
+def test_trained_network_cuts_iterations(c4small):
+    ok = lib()
+    L = c4small
+    assert L.loss < 0.3
+    for k in range(2):
+        xi = L.xi_eval[k]
+        rc0, st0, x0 = solve(L, xi, low=ok.OK_F32)
+        rc1, st1, x1 = solve(L, xi, low=ok.OK_F32, net=L.net)
+        assert rc0 == rc1 == ok.OK_SUCCESS
+        assert st1[0]["fallbacks"] == 0 and st1[0]["net_applies"] == 2 * st1[0]["iterations"]
+        assert st1[0]["iterations"] < 0.6 * st0[0]["iterations"], (st0[0]["iterations"], st1[0]["iterations"])
+        assert oracle_resid(L.U, L.c, xi, x1) <= ORACLE_SLACK * TOL
+
+
+@pytest.mark.parametrize("low", [1, 2], ids=["f32", "bf16"])
+def test_batched_with_network(c4small, low):
+    ok = lib()
+    L = c4small
+    rc0, st0, _ = solve(L, L.xi_eval, low=low | SITE)
+    rc1, st1, x = solve(L, L.xi_eval, low=low | SITE, net=L.net)
+    assert rc0 == rc1 == ok.OK_SUCCESS
+    for k in range(4):
+        assert st1[k]["fallbacks"] == 0
+        assert st1[k]["iterations"] < 0.6 * st0[k]["iterations"]
+        assert oracle_resid(L.U, L.c, L.xi_eval[k], x[k]) <= ORACLE_SLACK * TOL
+
+
+@pytest.mark.parametrize("bad", ["zero", "nan"])
+@pytest.mark.parametrize("low", [1, 1 | 0x10], ids=["single", "batched"])
+def test_failing_network_falls_back(c4small, bad, low):
+    """A zero network breaks the recurrence down at once (v = M N p = 0); a NaN network makes it
+    non-finite.  Either way the unpreconditioned solve takes over and converges."""
+    ok = lib()
+    L = c4small
+    torch = L.torch
+    n = ok.ok_net_param_count(2)
+    p = torch.zeros(n, dtype=torch.float32, device="cuda")
+    if bad == "nan":
+        p.fill_(float("nan"))
+    net = ok.Net(2, p, L.net.T)
+    xi = L.xi_eval[:2] if low & SITE else L.xi_eval[0]
+    rc, st, x = solve(L, xi, low=low, net=net)
+    assert rc == ok.OK_SUCCESS
+    xs = x if low & SITE else x[None]
+    xis = xi if low & SITE else xi[None]
+    for k in range(len(st)):
+        assert st[k]["fallbacks"] == 1
+        assert oracle_resid(L.U, L.c, xis[k], xs[k]) <= ORACLE_SLACK * TOL
+
+
+def test_network_needs_low_precision_solve(c4small):
+    ok = lib()
+    with pytest.raises(ok.OkError) as e:
+        solve(c4small, c4small.xi_eval[0], net=c4small.net)
+    assert e.value.status == ok.OK_EINVAL
