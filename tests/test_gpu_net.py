@@ -212,8 +212,8 @@ def test_adam_matches_oracle():
 
 
 def test_train_step_decreases_loss_and_matches_oracle_step(nl):
-    """One fused training step equals the oracle's gradient followed by its Adam step; ten steps
-    lower the loss on pairs (xi, psi = N0 xi) of a fixed target network N0."""
+    """One fused training step equals the oracle's gradient followed by its Adam step, and ten
+    steps follow the oracle's trajectory on pairs (xi, psi = N0 xi) of a fixed target network N0."""
     ok = nl.ok
     torch = nl.torch
     nf = 4
@@ -238,10 +238,15 @@ def test_train_step_decreases_loss_and_matches_oracle_step(nl):
     got = ok.to_host_complex(d_p, params.shape)
     big = (np.abs(G.real) > 1e-3 * np.abs(G).max())
     assert np.max(np.abs(got.real - p1.real)[big]) < 1e-5
+    # nine more steps follow the oracle's Adam trajectory (the loss of step t is taken before its update)
+    p, m, v = p1, (1 - 0.9) * 2 * G, (1 - 0.999) * ((2 * G.real) ** 2 + 1j * (2 * G.imag) ** 2)
     for step in range(2, 11):
         ok.ok_net_train_step(nl.dims, 2, d_p, d_m, d_v, nl.T, d_xi, d_psi, nf, 0, cfg, step, loss, grad, work)
+        Lt, Gt = N.loss_and_grad(nl.P, p, xi, psi)
+        p, m, v = N.adam_step(p, Gt, m, v, step, 3e-3)
     nl.sync()
-    assert loss.item() < 0.8 * L0
+    assert Lt < L0
+    assert abs(loss.item() - Lt) / Lt < 1e-3
 
 
 def test_full_size_layer_sampled():
