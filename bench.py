@@ -208,6 +208,133 @@ def cpu_baseline():
     }
 
 
+def learned(args):
+    """C4 / C5: the learned preconditioner, trained on the GPU on the same gauge field.
+
+    c4: 24^3x64, 256 training pairs, 64 fresh Gaussian evaluation sources; each solved
+        plain (FP64, unpreconditioned), mixed (FP32 W + FP64 reliable updates) with and without
+        the network, and in batches of 16 (BF16 site-major W on the matrix cores) with and
+        without the network.
+    c5: 32^3x64, 12 point sources: plain FP64 one after the other vs the network + batched BF16
+        on the matrix cores (12 together); the network is trained on 64 Gaussian pairs.
+    Training pairs come from the batched solver: FP64 solutions with true residual <= 1e-10,
+    the same criterion the plain solver stops at."""
+    import torch
+
+    from paper_1311_5029_amd import inputs as I
+    from paper_1311_5029_amd import okinv as ok
+    from paper_1311_5029_amd import train as TR
+
+    torch.cuda.set_device(0)
+    c4 = args.workload == "c4"
+    dims = tuple(args.dims) if args.dims else ((24, 24, 24, 64) if c4 else (32, 32, 32, 64))
+    V = int(np.prod(dims))
+    n_train = args.n_train or (256 if c4 else 64)
+    n_eval = args.n_eval or (64 if c4 else 12)
+    SITE = ok.OK_LAYOUT_SITE
+    log("%s: links %s" % (args.workload, dims))
+    cfg = I.make_config("C4" if c4 else "C5", dims=dims, with_sources=False)
+    c = cfg["coeffs"]
+    links = ok.to_device_complex(cfg["U"])
+    del cfg["U"]
+    Ws = {}
+    pre = {}
+    for prec in ([ok.OK_F64, ok.OK_F32, ok.OK_BF16 | SITE] if c4 else [ok.OK_F64, ok.OK_BF16 | SITE]):
+        Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(dims, prec))
+        scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(dims))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ok.ok_precompute_W(dims, c, links, prec, Ws[prec], scr)
+        torch.cuda.synchronize()
+        pre[prec] = time.perf_counter() - t
+        del scr
+    T = ok.empty_bytes(ok.ok_net_transports_bytes(dims))
+    ok.ok_net_transports(dims, links, T)
+    del links
+    log("precompute s %s" % {k: round(v, 3) for k, v in pre.items()})
+
+    lowb = ok.OK_BF16 | SITE
+    xi32, psi32, pinfo = TR.solve_pairs(dims, c, Ws[ok.OK_F64], Ws[lowb], lowb, n_train, I.SEED_TRAIN, log=log)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    net, hist = TR.train(dims, T, xi32, psi32, n_train, 1.0 / c.mhat, n_layers=4, steps=args.train_steps,
+                         batch=16 if c4 else 8, lr=3e-3, log=log)
+    train_s = time.perf_counter() - t
+    del xi32, psi32
+    torch.cuda.empty_cache()
+
+    def run(xi_host, low, with_net, nrhs):
+        lp = -1 if low is None else low
+        nn = net if with_net else None
+        work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(dims, nrhs, lp, nn))
+        d_xi = ok.to_device_complex(xi_host)
+        psi = torch.zeros_like(d_xi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10), Ws[ok.OK_F64],
+                                None if low is None else Ws[low], lp, d_xi, psi, nrhs, work, net=nn)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, rc, st
+
+    forms = {}
+
+    def add(name, sec, rc, st):
+        f = forms.setdefault(name, {"seconds": [], "iterations": [], "status": [], "resid": [], "fallbacks": 0})
+        f["seconds"].append(sec)
+        f["iterations"].extend(s["iterations"] for s in st)
+        f["status"].append(rc)
+        f["resid"].extend(s["true_rel_resid"] for s in st)
+        f["fallbacks"] += sum(s["fallbacks"] for s in st)
+
+    if c4:
+        for j, xi in enumerate(I.gaussian_source_batches(dims, n_eval, I.SEED_EVAL, 16)):
+            for k in range(xi.shape[0]):
+                for name, low, wn in (("plain_f64", None, False), ("mixed_f32", ok.OK_F32, False),
+                                      ("mixed_f32_net", ok.OK_F32, True)):
+                    add(name, *run(xi[k], low, wn, 1))
+            for name, wn in (("batched_bf16", False), ("batched_bf16_net", True)):
+                add(name, *run(xi, lowb, wn, xi.shape[0]))
+            log("evaluated %d/%d: %s" % (min(n_eval, 16 * (j + 1)), n_eval,
+                                         {k: (round(float(np.mean(v["iterations"])), 1), round(sum(v["seconds"]), 2))
+                                          for k, v in forms.items()}))
+    else:
+        xi = I.point_sources(dims)
+        for k in range(12):
+            add("plain_f64", *run(xi[k], None, False, 1))
+        add("batched_bf16", *run(xi, lowb, False, 12))
+        add("batched_bf16_net", *run(xi, lowb, True, 12))
+        log("evaluated: %s" % {k: (round(float(np.mean(v["iterations"])), 1), round(sum(v["seconds"]), 2))
+                               for k, v in forms.items()})
+
+    summary = {}
+    for name, f in forms.items():
+        summary[name] = {"seconds_total": round(sum(f["seconds"]), 3),
+                         "seconds_per_source": round(sum(f["seconds"]) / len(f["iterations"]), 4),
+                         "iterations_mean": round(float(np.mean(f["iterations"])), 2),
+                         "iterations_median": float(np.median(f["iterations"])),
+                         "all_converged": all(r == ok.OK_SUCCESS for r in f["status"]),
+                         "max_true_rel_resid": max(f["resid"]), "fallbacks": f["fallbacks"]}
+    plain = summary["plain_f64"]["seconds_per_source"]
+    out = {
+        "metric": "time to 1e-10 residual per source, plain FP64 vs learned preconditioner",
+        "workload": "%s: %dx%dx%dx%d, plaquette 0.6 links, %d %s sources" % (
+            args.workload.upper(), *dims, n_eval if c4 else 12, "Gaussian evaluation" if c4 else "point"),
+        "n_gpus": 1, "unit": "s/source", "higher_is_better": False,
+        "value": summary["batched_bf16_net"]["seconds_per_source"],
+        "speedup_vs_plain": {k: round(plain / v["seconds_per_source"], 3) for k, v in summary.items()},
+        "forms": summary,
+        "network": {"layers": 4, "hops": 27, "params_real": ok.ok_net_param_count(4), "precision": "f32",
+                    "training_pairs": n_train, "pair_solves": {k: (round(v, 3) if isinstance(v, float) else v)
+                                                               for k, v in pinfo.items()},
+                    "train_steps": args.train_steps, "train_seconds": round(train_s, 3),
+                    "loss_history": hist},
+        "precompute_seconds": {str(k): round(v, 3) for k, v in pre.items()},
+        "u0": round(cfg["u0"], 6), "eps": round(cfg["eps"], 6),
+        "data": "synthetic: random SU(3) links at plaquette 0.6; stand-in OK coefficients",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +348,12 @@ def main():
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
+                    help="c3 (default): the M.psi bench line; c4/c5: learned-preconditioner solves")
+    ap.add_argument("--dims", type=int, nargs=4, help="override the c4/c5 lattice (Lx Ly Lz Lt)")
+    ap.add_argument("--n-train", type=int, default=0)
+    ap.add_argument("--n-eval", type=int, default=0)
+    ap.add_argument("--train-steps", type=int, default=400)
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
@@ -232,6 +365,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d refused)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload != "c3":
+        learned(args)
+        return
 
     import torch
 

@@ -283,6 +283,10 @@ int ok_net_loss_and_grad(const ok_geom* g, const ok_net* net, const float* d_xi,
                          int nfields, int flags, double* d_loss, float* d_grad, void* d_work, size_t work_bytes,
                          void* stream);
 
+/* d_out[i] = (float) d_in[i] for n reals, round to nearest (e.g. FP64 training pairs
+ * from ok_bicgstab to the network's FP32 fields).  Asynchronous. */
+int ok_cast_f64_to_f32(const double* d_in, float* d_out, size_t n, void* stream);
+
 /* Adam on n real parameters d_p with Wirtinger gradient d_g (the real
  * gradient is 2 d_g) and moments d_m, d_v (zero before step 1); step >= 1.
  * Asynchronous. */

@@ -111,17 +111,6 @@ def loss_and_grad(P, params, xi, psi):
     return L, np.stack(grads)
 
 
-def init_params(n_layers, scale, seed, noise=1e-3):
-    """Identity-like start: layer 0 is scale * 1 on the on-site hop, later layers the identity,
-    plus small complex Gaussian noise on every weight (seeded)."""
-    rng = np.random.default_rng(seed)
-    p = noise * (rng.standard_normal((n_layers, 27, 4, 4)) + 1j * rng.standard_normal((n_layers, 27, 4, 4)))
-    p[0, 0] += scale * np.eye(4)
-    for l in range(1, n_layers):
-        p[l, 0] += np.eye(4)
-    return p
-
-
 def adam_step(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     """Adam on the real and imaginary parts: the real gradients are 2 Re g and 2 Im g."""
     gr = 2.0 * g

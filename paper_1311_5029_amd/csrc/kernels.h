@@ -143,6 +143,7 @@ int launch_net_wgrad(const Geo& g, int nf, bool inner, const float* T, const flo
 // loss and gout = dL/d(conj out); scratch holds net_loss_partial_bytes
 int launch_net_loss_grad(const Geo& g, int nf, bool inner, const float* out, const float* psi, float* gout,
                          double* loss, void* scratch, hipStream_t st);
+int launch_cast(long n, const double* in, float* out, hipStream_t st);
 int launch_adam(long n, float* p, const float* g, float* m, float* v, const ok_adam_cfg& c, int step,
                 hipStream_t st);
 

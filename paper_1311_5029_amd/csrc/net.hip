@@ -425,6 +425,11 @@ __global__ void __launch_bounds__(BS) k_adam(long n, float* __restrict__ p, cons
     p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
+__global__ void __launch_bounds__(BS) k_cast(long n, const double* __restrict__ in, float* __restrict__ out) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
 unsigned layer_grid(const Geo& g, int nf) { return grid_for((long)g.V * nf, BS); }
 
 }  // namespace
@@ -495,6 +500,12 @@ int launch_net_loss_grad(const Geo& g, int nf, bool inner, const float* out, con
     if (inner) k_loss_grad<true><<<layer_grid(g, nf), BS, 0, st>>>(g, nf, o, p, scale, go);
     else k_loss_grad<false><<<layer_grid(g, nf), BS, 0, st>>>(g, nf, o, p, scale, go);
     OK_LAUNCH_CHECK("k_loss_grad");
+    return OK_SUCCESS;
+}
+
+int launch_cast(long n, const double* in, float* out, hipStream_t st) {
+    k_cast<<<grid_for(n, BS), BS, 0, st>>>(n, in, out);
+    OK_LAUNCH_CHECK("k_cast");
     return OK_SUCCESS;
 }
 

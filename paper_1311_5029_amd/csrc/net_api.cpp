@@ -304,6 +304,20 @@ int ok_net_loss_and_grad(const ok_geom* g, const ok_net* net, const float* d_xi,
                          d_loss, d_grad, W, reinterpret_cast<hipStream_t>(stream));
 }
 
+int ok_cast_f64_to_f32(const double* d_in, float* d_out, size_t n, void* stream) {
+    NET_TRY(check_ptr(d_in, "d_in"));
+    NET_TRY(check_ptr(d_out, "d_out"));
+    if (n == 0 || n > (size_t)1 << 40) {
+        set_error("n = %zu outside [1, 2^40]", n);
+        return OK_EINVAL;
+    }
+    if (overlaps(d_in, n * 8, d_out, n * 4)) {
+        set_error("d_out must not overlap d_in");
+        return OK_EINVAL;
+    }
+    return launch_cast((long)n, d_in, d_out, reinterpret_cast<hipStream_t>(stream));
+}
+
 int ok_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, size_t n, const ok_adam_cfg* cfg, int step,
                  void* stream) {
     NET_TRY(check_ptr(d_p, "d_p"));

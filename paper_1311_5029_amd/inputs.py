@@ -2,7 +2,8 @@
 
 This module is shared by the CPU oracle and the GPU path and therefore holds
 none of the operator's arithmetic: it only draws gauge fields, sources, gauge
-transformations and coefficient sets, all on the host with NumPy's PCG64.
+transformations, coefficient sets and the preconditioner network's initial
+parameters, all on the host with NumPy's PCG64.
 
 Array conventions (shared by both sides):
 
@@ -131,6 +132,16 @@ def gaussian_sources(dims, nrhs, seed):
     return (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) / math.sqrt(2.0)
 
 
+def gaussian_source_batches(dims, n, seed, batch):
+    """The same distribution as gaussian_sources, drawn in batches of at most `batch` sources
+    so that large sets never sit on the host at once: batch j comes from the generator
+    seeded with (seed, j).  Yields arrays (nb, Lt, Lz, Ly, Lx, 4, 3) complex128."""
+    for j, k0 in enumerate(range(0, n, batch)):
+        rng = np.random.default_rng([seed, j])
+        shp = (min(batch, n - k0),) + lattice_shape(dims) + (4, 3)
+        yield (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) / math.sqrt(2.0)
+
+
 def point_sources(dims, origin=(0, 0, 0, 0)):
     """The 12 spin-colour point sources xi^(beta,b)_x = delta_{x,origin} delta_{alpha beta} delta_{ab}.
 
@@ -243,8 +254,9 @@ def config_epsilon(spec):
     return _EPS_CACHE[spec]
 
 
-def make_config(name, dims=None):
-    """Links, u0, coefficients and sources of a named workload (optionally at other dims)."""
+def make_config(name, dims=None, with_sources=True):
+    """Links, u0, coefficients and sources (None unless with_sources) of a named workload
+    (optionally at other dims)."""
     cfg = CONFIGS[name]
     d = tuple(dims) if dims is not None else cfg["dims"]
     num = int(name[1:])
@@ -252,8 +264,23 @@ def make_config(name, dims=None):
     U = random_su3_links(d, eps, SEED_LINKS + num)
     u0 = tadpole_u0(U)
     coeffs = standin_coeffs(m0=0.5, u0=u0)
-    if cfg["sources"] == "point":
+    if not with_sources:
+        xi = None
+    elif cfg["sources"] == "point":
         xi = point_sources(d)
     else:
         xi = gaussian_sources(d, cfg["nrhs"], SEED_SOURCES + num)
     return dict(dims=d, eps=eps, U=U, u0=u0, coeffs=coeffs, xi=xi)
+
+
+def net_init_params(n_layers, scale, seed=SEED_NET, noise=1e-3):
+    """Initial parameters of the preconditioner network, complex128 (n_layers, 27, 4, 4)
+    (hop k, spin out, spin in): the first layer scale * 1 on the on-site hop, later layers
+    the identity, plus complex Gaussian noise of size `noise` on every weight."""
+    rng = np.random.default_rng(seed)
+    shape = (n_layers, 27, 4, 4)
+    p = noise * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    p[0, 0] += scale * np.eye(4)
+    for l in range(1, n_layers):
+        p[l, 0] += np.eye(4)
+    return p

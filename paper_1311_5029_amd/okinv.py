@@ -89,6 +89,7 @@ _sig = {
     "ok_net_loss_grad": ([C.POINTER(ok_geom), _P, _P, _P, _P, C.c_int, C.c_int, _P, C.c_size_t, _P], C.c_int),
     "ok_net_loss_and_grad": ([C.POINTER(ok_geom), _NET, _P, _P, C.c_int, C.c_int, _P, _P, _P, C.c_size_t, _P],
                              C.c_int),
+    "ok_cast_f64_to_f32": ([_P, _P, C.c_size_t, _P], C.c_int),
     "ok_adam_step": ([_P, _P, _P, _P, C.c_size_t, C.POINTER(ok_adam_cfg), C.c_int, _P], C.c_int),
     "ok_net_train_step": ([C.POINTER(ok_geom), C.c_int, _P, _P, _P, _P, _P, _P, C.c_int, C.c_int,
                            C.POINTER(ok_adam_cfg), C.c_int, _P, _P, _P, C.c_size_t, _P], C.c_int),
@@ -281,6 +282,10 @@ def ok_net_loss_and_grad(dims, net, d_xi, d_psi, nfields, flags, d_loss, d_grad,
     return _check(_lib.ok_net_loss_and_grad(C.byref(geom(dims)), _netp(net), _ptr(d_xi), _ptr(d_psi), nfields,
                                             flags, _ptr(d_loss), _ptr(d_grad), _ptr(d_work), _nbytes(d_work),
                                             _stream(stream)))
+
+
+def ok_cast_f64_to_f32(d_in, d_out, n, stream=None):
+    return _check(_lib.ok_cast_f64_to_f32(_ptr(d_in), _ptr(d_out), n, _stream(stream)))
 
 
 def adam_cfg(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

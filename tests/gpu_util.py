@@ -82,28 +82,16 @@ def maxrel(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
-def train_net(L, xi, psi, n_layers=4, steps=200, lr=3e-3, seed=6000, batch=8):
-    """Train the preconditioner network on the GPU (fused training steps through the C-ABI) on
-    pairs (xi, psi = M^-1 xi) shaped (B, Lt, Lz, Ly, Lx, 4, 3); returns (okinv.Net, last loss).
-    Mini-batches are consecutive slices of `batch` pairs, cycled in order."""
-    from oracle.net import init_params
-    ok, torch = L.ok, L.torch
+def train_net(L, xi, psi, n_layers=4, steps=200, lr=3e-3, batch=8):
+    """Train the preconditioner network on the GPU with the package's training driver on host
+    pairs (xi, psi = M^-1 xi) shaped (B, Lt, Lz, Ly, Lx, 4, 3); returns (okinv.Net, last loss)."""
+    from paper_1311_5029_amd import train
+    ok = L.ok
     if not hasattr(L, "netT"):
         L.netT = ok.empty_bytes(ok.ok_net_transports_bytes(L.dims))
         ok.ok_net_transports(L.dims, L.links, L.netT)
-    p0 = init_params(n_layers, 1.0 / L.c.mhat, seed, noise=1e-3)
-    d_p = ok.to_device_complex(p0, dtype="float32")
-    d_m, d_v = torch.zeros_like(d_p), torch.zeros_like(d_p)
-    grad = torch.empty_like(d_p)
-    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    nb = xi.shape[0] // batch
-    d_xi = [ok.to_device_complex(xi[i * batch:(i + 1) * batch], dtype="float32") for i in range(nb)]
-    d_psi = [ok.to_device_complex(psi[i * batch:(i + 1) * batch], dtype="float32") for i in range(nb)]
-    work = ok.empty_bytes(ok.ok_net_workspace_bytes(L.dims, n_layers, batch, 1))
-    cfg = ok.adam_cfg(lr=lr)
-    for step in range(1, steps + 1):
-        i = (step - 1) % nb
-        ok.ok_net_train_step(L.dims, n_layers, d_p, d_m, d_v, L.netT, d_xi[i], d_psi[i], batch, 0, cfg, step,
-                             loss, grad, work)
-    torch.cuda.synchronize()
-    return ok.Net(n_layers, d_p, L.netT), loss.item()
+    xi32 = ok.to_device_complex(xi, dtype="float32")
+    psi32 = ok.to_device_complex(psi, dtype="float32")
+    net, hist = train.train(L.dims, L.netT, xi32, psi32, xi.shape[0], 1.0 / L.c.mhat, n_layers=n_layers,
+                            steps=steps, batch=batch, lr=lr)
+    return net, hist[-1][1]

@@ -160,7 +160,7 @@ def test_loss_and_output_gradient(nl, inner):
 @pytest.mark.parametrize("nf,inner", [(3, False), (6, True)], ids=["outer3", "inner6"])
 def test_network_apply(nl, nf, inner):
     ok = nl.ok
-    params = N.init_params(4, 0.5, 100, noise=0.1)
+    params = I.net_init_params(4, 0.5, 100, noise=0.1)
     net = ok.Net(4, nl.params(params), nl.T)
     phi = I.gaussian_sources(nl.dims, nf, 101)
     d_in = nl.up(phi, inner)
@@ -174,7 +174,7 @@ def test_network_apply(nl, nf, inner):
 @pytest.mark.parametrize("nf,inner", [(2, False), (5, True)], ids=["outer2", "inner5"])
 def test_loss_and_parameter_gradient(nl, nf, inner):
     ok = nl.ok
-    params = N.init_params(3, 0.4, 102, noise=0.1)
+    params = I.net_init_params(3, 0.4, 102, noise=0.1)
     xi = I.gaussian_sources(nl.dims, nf, 103)
     psi = I.gaussian_sources(nl.dims, nf, 104)
     net = ok.Net(3, nl.params(params), nl.T)
@@ -217,8 +217,8 @@ def test_train_step_decreases_loss_and_matches_oracle_step(nl):
     ok = nl.ok
     torch = nl.torch
     nf = 4
-    target = N.init_params(2, 0.5, 106, noise=0.2)
-    params = N.init_params(2, 0.5, 107, noise=0.05)
+    target = I.net_init_params(2, 0.5, 106, noise=0.2)
+    params = I.net_init_params(2, 0.5, 107, noise=0.05)
     xi = I.gaussian_sources(nl.dims, nf, 108)
     psi = N.forward(nl.P, target, xi)[-1]
     d_p = nl.params(params)

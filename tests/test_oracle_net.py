@@ -14,7 +14,7 @@ DIMS = (4, 5, 4, 6)
 def setup():
     U = I.random_su3_links(DIMS, 0.4, 81)
     P = net.all_transports(U)
-    params = net.init_params(3, 0.3, 82, noise=0.05)
+    params = I.net_init_params(3, 0.3, 82, noise=0.05)
     return U, P, params
 
 
