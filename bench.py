@@ -246,7 +246,7 @@ def learned(args):
         t = time.perf_counter()
         ok.ok_precompute_W(dims, c, links, prec, Ws[prec], scr)
         torch.cuda.synchronize()
-        pre[prec] = time.perf_counter() - t
+        pre[PREC_NAME[prec & 3] + ("_site" if prec & SITE else "")] = time.perf_counter() - t
         del scr
     T = ok.empty_bytes(ok.ok_net_transports_bytes(dims))
     ok.ok_net_transports(dims, links, T)
@@ -324,11 +324,10 @@ def learned(args):
         "speedup_vs_plain": {k: round(plain / v["seconds_per_source"], 3) for k, v in summary.items()},
         "forms": summary,
         "network": {"layers": 4, "hops": 27, "params_real": ok.ok_net_param_count(4), "precision": "f32",
-                    "training_pairs": n_train, "pair_solves": {k: (round(v, 3) if isinstance(v, float) else v)
-                                                               for k, v in pinfo.items()},
+                    "training_pairs": n_train, "pair_solves": pinfo,
                     "train_steps": args.train_steps, "train_seconds": round(train_s, 3),
                     "loss_history": hist},
-        "precompute_seconds": {str(k): round(v, 3) for k, v in pre.items()},
+        "precompute_seconds": {k: round(v, 3) for k, v in pre.items()},
         "u0": round(cfg["u0"], 6), "eps": round(cfg["eps"], 6),
         "data": "synthetic: random SU(3) links at plaquette 0.6; stand-in OK coefficients",
     }
