@@ -334,6 +334,65 @@ def learned(args):
     print(json.dumps(out), flush=True)
 
 
+def net_kernels(args):
+    """The network kernels alone at 24^3x64: one layer on 1 field ([V][12]) and on 16 fields
+    (right-hand side fastest), its adjoint, and the weight gradient; HIP events on the
+    library's stream.  Bytes: 936 B of transports per site (13 forward 3x3 FP32 complex;
+    the backward hops reread them at the neighbour) + 96 B in and 96 B out per field;
+    flops: 26 hops x (36 + 48) + 48 complex multiply-adds = 17,856 per site and field."""
+    import torch
+
+    from paper_1311_5029_amd import inputs as I
+    from paper_1311_5029_amd import okinv as ok
+
+    torch.cuda.set_device(0)
+    dims = tuple(args.dims) if args.dims else (24, 24, 24, 64)
+    V = int(np.prod(dims))
+    log("net kernels at %s" % (dims,))
+    U = I.random_su3_links(dims, I.config_epsilon("plaq0.6"), I.SEED_LINKS + 4)
+    links = ok.to_device_complex(U)
+    del U
+    T = ok.empty_bytes(ok.ok_net_transports_bytes(dims))
+    ok.ok_net_transports(dims, links, T)
+    del links
+    A = ok.to_device_complex(I.net_init_params(1, 1.0, I.SEED_NET, noise=0.1)[0], dtype="float32")
+    stream = torch.cuda.current_stream()
+    out = {"metric": "network layer throughput", "lattice": list(dims), "kernels": {}}
+    flops_site = 26 * (36 + 48) * 8 + 48 * 8
+
+    def timed(fn, n=10):
+        for _ in range(2):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    for nf, inner in ((1, False), (16, True)):
+        x = torch.randn(nf * V * 24, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        fl = ok.OK_SPINOR_RHS_INNER if inner else 0
+        gA = torch.empty(27 * 32, dtype=torch.float32, device="cuda")
+        work = ok.empty_bytes(ok.ok_net_workspace_bytes(dims, 1, nf, 2))
+        for name, fn in (("layer", lambda: ok.ok_net_layer(dims, A, T, x, y, nf, fl, stream)),
+                         ("adjoint", lambda: ok.ok_net_layer(dims, A, T, x, y, nf, fl | ok.OK_NET_ADJOINT, stream)),
+                         ("wgrad", lambda: ok.ok_net_layer_wgrad(dims, T, x, y, gA, nf, fl, work, stream))):
+            ms = timed(fn)
+            by = V * (936 + nf * 192)
+            fl_ = V * nf * flops_site
+            key = "%s_nf%d_%s" % (name, nf, "inner" if inner else "outer")
+            out["kernels"][key] = {"ms": round(ms, 4), "GB/s": round(by / ms / 1e6, 1),
+                                   "TFLOP/s": round(fl_ / ms / 1e9, 2),
+                                   "frac_hbm": round(by / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                   "frac_fp32_valu": round(fl_ / ms / 1e9 / 157.3, 4)}
+            log("%s %s" % (key, out["kernels"][key]))
+        del x, y, work
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,8 +406,9 @@ def main():
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 --kernel-trace --stats run and exit")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
-                    help="c3 (default): the M.psi bench line; c4/c5: learned-preconditioner solves")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "net"],
+                    help="c3 (default): the M.psi bench line; c4/c5: learned-preconditioner solves; "
+                         "net: the network kernels alone")
     ap.add_argument("--dims", type=int, nargs=4, help="override the c4/c5 lattice (Lx Ly Lz Lt)")
     ap.add_argument("--n-train", type=int, default=0)
     ap.add_argument("--n-eval", type=int, default=0)
@@ -364,6 +424,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d refused)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "net":
+        net_kernels(args)
+        return
     if args.workload != "c3":
         learned(args)
         return

@@ -230,7 +230,10 @@ __global__ void __launch_bounds__(BS, 2) k_apply_mrhs(Geo g, const uint4* __rest
 // Spinor layout SL = 0: [nrhs][V][12] complex (the ABI default);
 // SL = 1 (OK_SPINOR_RHS_INNER): [V][12][nrhs] complex, so the 12 right-hand
 // sides of one component are adjacent and a step's B operand is contiguous.
-constexpr int SPW_SITE = 2;     // sites per wavefront
+#ifndef OKINV_SITE_SPW
+#define OKINV_SITE_SPW 2
+#endif
+constexpr int SPW_SITE = OKINV_SITE_SPW;     // sites per wavefront
 
 template <int SL>
 __device__ __forceinline__ size_t sp_index(int nrhs, size_t V, int j, int s, int c) {
@@ -343,7 +346,10 @@ __device__ __forceinline__ void mma_ops(const Ops<P>& o, int l16, int grp, v4f& 
 }
 
 // Prefetch depth: operands of DEPTH offsets are in flight ahead of the MFMAs.
-constexpr int DEPTH = 4;
+#ifndef OKINV_SITE_DEPTH
+#define OKINV_SITE_DEPTH 4
+#endif
+constexpr int DEPTH = OKINV_SITE_DEPTH;
 
 template <int P, int SL>
 __global__ void __launch_bounds__(256) k_apply_site(Geo g, const uint4* __restrict__ W,
