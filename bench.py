@@ -162,16 +162,18 @@ def summarize_trace(d, out_path, command):
         name = r["Name"].replace("okinv::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
         name = re.sub(r"\(.*", "", name).replace("void ", "")[:44]
         lines.append("%-44s %6s %14.0f %8.2f" % (name, r["Calls"], float(r["AverageNs"]), float(r["Percentage"])))
-    for form, prec in (("f64", 0), ("f32", 1), ("bf16", 2)):
-        for r in rows:
-            if is_apply_kernel(r["Name"], form):
-                ns = float(r["AverageNs"])
-                gbs = BYTES_SITE[prec] * V / ns
-                lines.append("")
-                lines.append("%s: %s average %.0f ns per launch -> %.1f GB/s algorithmic (%d B/site x %d sites), "
-                             "%.1f%% of 8 TB/s" % (form, re.sub(r"\(.*", "", r["Name"].split("::")[-1]), ns, gbs,
-                                                   BYTES_SITE[prec], V, gbs / HBM_PEAK_GBS * 100))
-                break
+    for kernel, per_site in (("k_apply", BYTES_SITE), ("k_apply_site", BYTES_STEP)):
+        for form, prec in (("f64", 0), ("f32", 1), ("bf16", 2)):
+            for r in rows:
+                if is_apply_kernel(r["Name"], form, kernel):
+                    ns = float(r["AverageNs"])
+                    gbs = per_site[prec] * V / ns
+                    lines.append("")
+                    lines.append("%s<%s> (%s): average %.0f ns per launch -> %.1f GB/s algorithmic "
+                                 "(%d B/site x %d sites), %.1f%% of 8 TB/s"
+                                 % (kernel, form, "1 RHS" if kernel == "k_apply" else "12 RHS", ns, gbs,
+                                    per_site[prec], V, gbs / HBM_PEAK_GBS * 100))
+                    break
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
