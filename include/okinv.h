@@ -174,7 +174,10 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const 
  *           Wlo_prec | OK_LAYOUT_SITE the right-hand sides (in groups of up to
  *           16) iterate together: one matrix-core application of W per
  *           BiCGStab step for the whole group, per-right-hand-side scalars,
- *           reliable updates and convergence.
+ *           reliable updates and convergence.  When a right-hand side is due
+ *           for a reliable update, every one whose residual has fallen below
+ *           sqrt(delta) of its maximum is updated in the same FP64 pass (W64
+ *           read once per four right-hand sides).
  *   net     NULL, or the learned preconditioner N (low-precision solves
  *           only): BiCGStab then runs right-preconditioned, each step
  *           applying N to the search direction and to s (p^ = N p,

@@ -57,6 +57,10 @@ int apply_blocks(const Geo& g, int tps);
 int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int tps,
                  int epi, const void* aux, double2* partial, hipStream_t st);
 
+// FP64 W on n separate FP64 right-hand sides (in[r] -> out[r]), W read once per four of them
+int launch_apply_m64(const Geo& g, const void* W, const double* const* in, double* const* out, int n, double mhat,
+                     hipStream_t st);
+
 // stencil_mrhs.hip: up to 16 right-hand sides per pass on MFMA (FP32 or BF16 W, FP32 spinors)
 int launch_apply_mrhs(const Geo& g, const void* W, int Wprec, const float* psi, float* out, double mhat,
                       int nrhs, hipStream_t st);

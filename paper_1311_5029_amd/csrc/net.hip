@@ -329,18 +329,26 @@ __global__ void __launch_bounds__(BS) k_wgrad(Geo g, int nf, int nch, const floa
     }
 }
 
-// Second pass: gA[k][e] = sum over ch of partial[ch][k][e], in FP64, ch in order.
+// Second pass: gA[i] = sum over ch of partial[ch][i] (i = 16 k + e), one wavefront per i:
+// lane l sums the chunks l, l + 64, ... in FP64, then the lanes are combined by a fixed
+// shuffle tree, so the result does not depend on timing.
 __global__ void __launch_bounds__(BS) k_wgrad_finish(int nch, const float2* __restrict__ partial,
                                                      float2* __restrict__ gA) {
-    const int i = blockIdx.x * BS + threadIdx.x;
+    const int i = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i >= 27 * 16) return;
     double x = 0.0, y = 0.0;
-    for (int ch = 0; ch < nch; ++ch) {
+    for (int ch = lane; ch < nch; ch += 64) {
         const float2 v = partial[(size_t)ch * 27 * 16 + i];
         x += v.x;
         y += v.y;
     }
-    gA[i] = make_float2((float)x, (float)y);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o, 64);
+        y += __shfl_xor(y, o, 64);
+    }
+    if (lane == 0) gA[i] = make_float2((float)x, (float)y);
 }
 
 // ------------------------------------------------------------------ loss
@@ -479,7 +487,7 @@ int launch_net_wgrad(const Geo& g, int nf, bool inner, const float* T, const flo
     if (inner) k_wgrad<true><<<grid, BS, 0, st>>>(g, nf, nch, t, go, i, p);
     else k_wgrad<false><<<grid, BS, 0, st>>>(g, nf, nch, t, go, i, p);
     OK_LAUNCH_CHECK("k_wgrad");
-    k_wgrad_finish<<<grid_for(27 * 16, BS), BS, 0, st>>>(nch, p, reinterpret_cast<float2*>(gA));
+    k_wgrad_finish<<<grid_for(27 * 16 * 64, BS), BS, 0, st>>>(nch, p, reinterpret_cast<float2*>(gA));
     OK_LAUNCH_CHECK("k_wgrad_finish");
     return OK_SUCCESS;
 }

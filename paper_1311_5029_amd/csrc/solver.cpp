@@ -350,7 +350,7 @@ size_t layout_batched(const Geo& g, int nrhs, int net_layers, char* base, WorkB*
     W.sc = reinterpret_cast<ScalB*>(take(sizeof(ScalB)));
     const int nb = std::max(kGridB, col_blocks(g));
     W.partial = reinterpret_cast<double2*>(take((size_t)nb * kMaxRhsB * 2 * sizeof(double2)));
-    W.t64 = reinterpret_cast<double*>(take((size_t)g.V * 12 * 16));
+    W.t64 = reinterpret_cast<double*>(take((size_t)4 * g.V * 12 * 16));   // four FP64 fields
     for (int i = 0; i < (net_layers ? 9 : 7); ++i) W.f[i] = reinterpret_cast<float*>(take((size_t)g.V * 12 * nrhs * 8));
     W.netw = net_layers ? take(net_apply_work_bytes(g, net_layers, nrhs)) : nullptr;
     return off;
@@ -372,18 +372,33 @@ int write_active(Ctx& C, WorkB& B, const ScalB* h) {
     return OK_SUCCESS;
 }
 
-// x64_j += x32[:, j]; r[:, j] = xi_j - M64 x64_j; returns ||r_j||^2 (FP64)
-int batched_true_residual(Ctx& C, WorkB& B, int nrhs, int j, const double* xi, double* x64, double* rr,
-                          ok_solver_stats* S) {
+// For every column j in cols[0..n): x64_j += x32[:, j]; r[:, j] = xi_j - M64 x64_j;
+// rr[j] = ||r_j||^2 in FP64.  xi and x are the bases of the [nrhs][V][12] FP64 fields.
+// The FP64 operator runs on up to four columns per pass, reading W once per pass.
+int batched_true_residuals(Ctx& C, WorkB& B, int nrhs, const int* cols, int n, const double* xi, double* x,
+                           double* rr, ok_solver_stats* S) {
     const Geo& g = C.g;
-    OK_TRY(launch_col_accum(g, nrhs, j, x64, B.f[0], C.st));
-    OK_TRY(launch_apply(g, C.W64, OK_F64, x64, B.t64, C.c->mhat, C.tps64, EPI_NONE, nullptr, nullptr, C.st));
-    S->matvec_hi++;
-    OK_TRY(launch_col_residual(g, nrhs, j, xi, B.t64, B.f[1], B.partial, C.st));
-    OK_TRY(bfin(C, B, FIN_TRUE, col_blocks(g), j, 1));
+    const size_t col = (size_t)g.V * 24;
+    for (int i = 0; i < n; ++i) OK_TRY(launch_col_accum(g, nrhs, cols[i], x + cols[i] * col, B.f[0], C.st));
+    for (int i0 = 0; i0 < n; i0 += 4) {
+        const int m = std::min(4, n - i0);
+        const double* in[4];
+        double* out[4];
+        for (int r = 0; r < m; ++r) {
+            in[r] = x + cols[i0 + r] * col;
+            out[r] = B.t64 + (size_t)r * col;
+        }
+        OK_TRY(launch_apply_m64(g, C.W64, in, out, m, C.c->mhat, C.st));
+        for (int r = 0; r < m; ++r) {
+            const int j = cols[i0 + r];
+            S[j].matvec_hi++;
+            OK_TRY(launch_col_residual(g, nrhs, j, xi + j * col, out[r], B.f[1], B.partial, C.st));
+            OK_TRY(bfin(C, B, FIN_TRUE, col_blocks(g), j, 1));
+        }
+    }
     ScalB h;
     OK_TRY(read_scalb(C, B, &h));
-    *rr = h.rr_true[j];
+    for (int i = 0; i < n; ++i) rr[cols[i]] = h.rr_true[cols[i]];
     return OK_SUCCESS;
 }
 
@@ -437,7 +452,9 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
             OK_TRY(launch_col_load(g, nrhs, j, xi + j * col, r, C.st));
             rr = xn[j] * xn[j];
         } else {
-            OK_TRY(batched_true_residual(C, B, nrhs, j, xi + j * col, x + j * col, &rr, &S[j]));
+            double rrv[kMaxRhsB];
+            OK_TRY(batched_true_residuals(C, B, nrhs, &j, 1, xi, x, rrv, S));
+            rr = rrv[j];
         }
         S[j].true_rel_resid = std::sqrt(rr) / xn[j];
         if (S[j].true_rel_resid <= P.tol) {
@@ -460,10 +477,14 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
     const int wp = C.Wlo_prec & ~OK_LAYOUT_SITE;
     while (any_active()) {
         if (it >= P.max_iter) {
+            int cols[kMaxRhsB], n = 0;
+            double rrv[kMaxRhsB];
+            for (int j = 0; j < nrhs; ++j)
+                if (h.active[j]) cols[n++] = j;
+            OK_TRY(batched_true_residuals(C, B, nrhs, cols, n, xi, x, rrv, S));
             for (int j = 0; j < nrhs; ++j) {
                 if (!h.active[j]) continue;
-                double rr;
-                OK_TRY(batched_true_residual(C, B, nrhs, j, xi + j * col, x + j * col, &rr, &S[j]));
+                const double rr = rrv[j];
                 S[j].true_rel_resid = std::sqrt(rr) / xn[j];
                 S[j].status = S[j].true_rel_resid <= P.tol ? OK_SUCCESS : OK_NOT_CONVERGED;
                 if (S[j].status != OK_SUCCESS && rc_all == OK_SUCCESS) rc_all = S[j].status;
@@ -489,12 +510,17 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
         OK_TRY(read_scalb(C, B, &hd));
         ++it;
         bool changed = false;
+        // pass 1: bookkeeping, failures, and which right-hand sides are due for a reliable update
+        bool due[kMaxRhsB] = {false};
+        double rnv[kMaxRhsB];
+        bool any_due = false;
         for (int j = 0; j < nrhs; ++j) {
             if (!h.active[j]) continue;
             S[j].iterations++;
             S[j].matvec_lo += 2;
             if (C.net) S[j].net_applies += 2;
             const double rn = std::sqrt(hd.rr[j]);
+            rnv[j] = rn;
             if (P.verbose) fprintf(stderr, "okinv batched it %d rhs %d |r|/|xi| %.3e\n", it, j, rn / xn[j]);
             if (C.net) {
                 if (rn < best[j]) {
@@ -516,34 +542,46 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
                 S[j].status = OK_ENONFINITE;
                 return OK_ENONFINITE;
             }
-            const bool broke = hd.flags[j] & 1;
             maxr[j] = std::max(maxr[j], rn);
-            if (!(rn < P.delta * maxr[j] || rn / xn[j] <= P.tol || broke)) continue;
-            double rr;
-            OK_TRY(batched_true_residual(C, B, nrhs, j, xi + j * col, x + j * col, &rr, &S[j]));
-            S[j].reliable_updates++;
-            const double rt = std::sqrt(rr);
-            S[j].true_rel_resid = rt / xn[j];
-            if (S[j].true_rel_resid <= P.tol) {
-                S[j].status = OK_SUCCESS;
-                h.active[j] = 0;
-                changed = true;
-                continue;
-            }
-            maxr[j] = rt;
-            if (broke) {
-                if (S[j].restarts >= P.max_restarts) {
-                    S[j].status = OK_BREAKDOWN;
-                    if (rc_all == OK_SUCCESS) rc_all = OK_BREAKDOWN;
+            due[j] = rn < P.delta * maxr[j] || rn / xn[j] <= P.tol || (hd.flags[j] & 1);
+            any_due |= due[j];
+        }
+        // pass 2: when any right-hand side is due, every one within sqrt(delta) of its maximum joins
+        // the same FP64 pass (one W read per four of them)
+        if (any_due) {
+            int cols[kMaxRhsB], n = 0;
+            const double dg = std::sqrt(P.delta);
+            for (int j = 0; j < nrhs; ++j)
+                if (h.active[j] && (due[j] || rnv[j] < dg * maxr[j])) cols[n++] = j;
+            double rrv[kMaxRhsB];
+            OK_TRY(batched_true_residuals(C, B, nrhs, cols, n, xi, x, rrv, S));
+            for (int i = 0; i < n; ++i) {
+                const int j = cols[i];
+                const bool broke = hd.flags[j] & 1;
+                S[j].reliable_updates++;
+                const double rt = std::sqrt(rrv[j]);
+                S[j].true_rel_resid = rt / xn[j];
+                if (S[j].true_rel_resid <= P.tol) {
+                    S[j].status = OK_SUCCESS;
                     h.active[j] = 0;
                     changed = true;
                     continue;
                 }
-                S[j].restarts++;
-                OK_TRY(batched_restart(C, B, nrhs, j));
-            } else {
-                OK_TRY(launch_col_dot(g, nrhs, j, rhat, r, B.partial, C.st));
-                OK_TRY(bfin(C, B, FIN_RHO_REPLACE, col_blocks(g), j, 1));
+                maxr[j] = rt;
+                if (broke) {
+                    if (S[j].restarts >= P.max_restarts) {
+                        S[j].status = OK_BREAKDOWN;
+                        if (rc_all == OK_SUCCESS) rc_all = OK_BREAKDOWN;
+                        h.active[j] = 0;
+                        changed = true;
+                        continue;
+                    }
+                    S[j].restarts++;
+                    OK_TRY(batched_restart(C, B, nrhs, j));
+                } else {
+                    OK_TRY(launch_col_dot(g, nrhs, j, rhat, r, B.partial, C.st));
+                    OK_TRY(bfin(C, B, FIN_RHO_REPLACE, col_blocks(g), j, 1));
+                }
             }
         }
         if (changed) OK_TRY(write_active(C, B, &h));

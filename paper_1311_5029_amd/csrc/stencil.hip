@@ -11,6 +11,8 @@
 // BiCGStab recurrence needs right after an application (see blas1.hip):
 //   EPI_RV:  <aux, out>                  (r^ . v)
 //   EPI_TS:  <out, in>, <out, out>      (t . s, t . t)
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "wlayout.h"
@@ -166,7 +168,84 @@ int launch_apply_t(const Geo& g, const void* W, const void* psi, void* out, doub
     return OK_SUCCESS;
 }
 
+// FP64 W (plane layout) applied to NR right-hand sides in one pass, out_r = mhat in_r + sum_k W_k in_r(x+d_k):
+// each W element is loaded once and multiplied into every right-hand side.  Four threads per site
+// (three output rows each); the right-hand sides are separate FP64 fields [V][12] named in `cols`.
+struct Cols64 {
+    const double* in[4];
+    double* out[4];
+};
+
+template <int NR>
+__global__ void __launch_bounds__(256) k_apply_m64(Geo g, const void* __restrict__ W, Cols64 cols, double mhat) {
+    constexpr int TPS = 4, RPT = 3, SPW = 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane / SPW;
+    const int s = (blockIdx.x * (blockDim.x >> 6) + wave) * SPW + (lane % SPW);
+    if (s >= g.V) return;
+    const int r0 = grp * RPT;
+    int x, y, z, t;
+    site_coords(g, s, x, y, z, t);
+    c128 acc[NR][RPT];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const double2* c = reinterpret_cast<const double2*>(cols.in[r]) + (size_t)s * 12 + r0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[r][q] = c128{mhat * c[q].x, mhat * c[q].y};
+    }
+    constexpr int ch = WL<OK_F64>::chunks;
+#pragma unroll 1
+    for (int k = 0; k < kW; ++k) {
+        const int n = neighbour(g, x, y, z, t, off_d(k, 0), off_d(k, 1), off_d(k, 2), off_d(k, 3));
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            c128 w[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const double2 d = ld_stream(reinterpret_cast<const double2*>(W) +
+                                            ((size_t)(k * ch + (r0 + q) * 12 + j)) * g.Vs + s);
+                w[q] = c128{d.x, d.y};
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const double2 v = reinterpret_cast<const double2*>(cols.in[r])[(size_t)n * 12 + j];
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) cfma(acc[r][q], w[q], c128{v.x, v.y});
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        double2* o = reinterpret_cast<double2*>(cols.out[r]) + (size_t)s * 12 + r0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) o[q] = make_double2(acc[r][q].re, acc[r][q].im);
+    }
+    (void)TPS;
+}
+
 }  // namespace
+
+int launch_apply_m64(const Geo& g, const void* W, const double* const* in, double* const* out, int n, double mhat,
+                     hipStream_t st) {
+    for (int r0 = 0; r0 < n; r0 += 4) {
+        const int nr = std::min(4, n - r0);
+        Cols64 c{};
+        for (int r = 0; r < nr; ++r) {
+            c.in[r] = in[r0 + r];
+            c.out[r] = out[r0 + r];
+        }
+        const unsigned nb = grid_for((long)g.V * 4, 256);
+        switch (nr) {
+            case 1: k_apply_m64<1><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+            case 2: k_apply_m64<2><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+            case 3: k_apply_m64<3><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+            default: k_apply_m64<4><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+        }
+        OK_LAUNCH_CHECK("k_apply_m64");
+    }
+    return OK_SUCCESS;
+}
 
 int apply_blocks(const Geo& g, int tps) {
     return (int)grid_for((long)g.V * tps, 256);
