@@ -336,6 +336,57 @@ def learned(args):
     print(json.dumps(out), flush=True)
 
 
+def mixed_c2(args):
+    """C2: 16^3x32, plaquette 0.6, one Gaussian source: plain FP64 BiCGStab vs FP32 (and BF16) W with
+    FP64 reliable updates, all to 1e-10; each mixed solution's error against the plain FP64 one."""
+    import torch
+
+    from paper_1311_5029_amd import inputs as I
+    from paper_1311_5029_amd import okinv as ok
+
+    torch.cuda.set_device(0)
+    dims = tuple(args.dims) if args.dims else (16, 16, 16, 32)
+    cfg = I.make_config("C2", dims=dims)
+    c = cfg["coeffs"]
+    links = ok.to_device_complex(cfg["U"])
+    Ws = {}
+    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
+        Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(dims, prec))
+        scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(dims))
+        ok.ok_precompute_W(dims, c, links, prec, Ws[prec], scr)
+        del scr
+    xi = ok.to_device_complex(cfg["xi"][0])
+    out = {"metric": "time to 1e-10 residual, plain FP64 vs mixed precision with FP64 reliable updates",
+           "workload": "C2: %dx%dx%dx%d, plaquette 0.6 links, one Gaussian source" % dims, "n_gpus": 1,
+           "unit": "s", "forms": {}}
+    sol = {}
+    for name, low in (("plain_f64", None), ("mixed_f32", ok.OK_F32), ("mixed_bf16", ok.OK_BF16)):
+        lp = -1 if low is None else low
+        work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(dims, 1, lp))
+        best = None
+        for _ in range(3):   # median of three solves
+            psi = torch.zeros_like(xi)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10), Ws[ok.OK_F64],
+                                    None if low is None else Ws[low], lp, xi, psi, 1, work)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t
+            best = sorted((best or []) + [sec])
+        sol[name] = psi
+        out["forms"][name] = {"seconds_median": round(best[1], 4), "status": rc, "iterations": st[0]["iterations"],
+                              "reliable_updates": st[0]["reliable_updates"],
+                              "true_rel_resid": st[0]["true_rel_resid"]}
+        log("%s %s" % (name, out["forms"][name]))
+    for name in ("mixed_f32", "mixed_bf16"):
+        err = float(torch.linalg.vector_norm(sol[name] - sol["plain_f64"]) /
+                    torch.linalg.vector_norm(sol["plain_f64"]))
+        out["forms"][name]["rel_error_vs_plain_f64"] = err
+        out["forms"][name]["speedup"] = round(out["forms"]["plain_f64"]["seconds_median"] /
+                                              out["forms"][name]["seconds_median"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def net_kernels(args):
     """The network kernels alone at 24^3x64: one layer on 1 field ([V][12]) and on 16 fields
     (right-hand side fastest), its adjoint, and the weight gradient; HIP events on the
@@ -408,9 +459,9 @@ def main():
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 --kernel-trace --stats run and exit")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "net"],
-                    help="c3 (default): the M.psi bench line; c4/c5: learned-preconditioner solves; "
-                         "net: the network kernels alone")
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "net"],
+                    help="c3 (default): the M.psi bench line; c2: plain vs mixed precision; "
+                         "c4/c5: learned-preconditioner solves; net: the network kernels alone")
     ap.add_argument("--dims", type=int, nargs=4, help="override the c4/c5 lattice (Lx Ly Lz Lt)")
     ap.add_argument("--n-train", type=int, default=0)
     ap.add_argument("--n-eval", type=int, default=0)
@@ -428,6 +479,9 @@ def main():
         sys.exit(2)
     if args.workload == "net":
         net_kernels(args)
+        return
+    if args.workload == "c2":
+        mixed_c2(args)
         return
     if args.workload != "c3":
         learned(args)

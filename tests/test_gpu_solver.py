@@ -307,3 +307,24 @@ def test_network_needs_low_precision_solve(c4small):
     with pytest.raises(ok.OkError) as e:
         solve(c4small, c4small.xi_eval[0], net=c4small.net)
     assert e.value.status == ok.OK_EINVAL
+
+
+def test_c2_full_size_mixed_vs_plain():
+    """The C2 workload at its size (16^3 x 32, plaquette 0.6, one Gaussian source): plain FP64 and
+    FP32 / BF16 W with FP64 reliable updates all reach the oracle's residual bound, and the mixed
+    solutions agree with the plain FP64 one to within the conditioning times the tolerance."""
+    ok = lib()
+    cfg = I.make_config("C2")
+    L = Lattice(cfg["dims"], cfg["U"], cfg["coeffs"])
+    xi = cfg["xi"][0]
+    rc, st, x64 = solve(L, xi)
+    assert rc == ok.OK_SUCCESS
+    assert oracle_resid(cfg["U"], cfg["coeffs"], xi, x64) <= ORACLE_SLACK * TOL
+    for low in (ok.OK_F32, ok.OK_BF16):
+        rc, st, x = solve(L, xi, low=low)
+        assert rc == ok.OK_SUCCESS and st[0]["reliable_updates"] >= 1
+        assert oracle_resid(cfg["U"], cfg["coeffs"], xi, x) <= ORACLE_SLACK * TOL
+        err = np.linalg.norm(x - x64) / np.linalg.norm(x64)
+        print("C2 %s: %d iterations, %d reliable updates, |x - x64|/|x64| = %.2e"
+              % ("f32" if low == ok.OK_F32 else "bf16", st[0]["iterations"], st[0]["reliable_updates"], err))
+        assert err < 1e-8
