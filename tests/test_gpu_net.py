@@ -286,3 +286,62 @@ def test_full_size_layer_sampled():
         want = N.layer(Pw, A, fw)[:, 2, 2, 2, 2]
         g = got[s, :, :, 0] + 1j * got[s, :, :, 1]      # (12, nf)
         assert rel(np.moveaxis(g, -1, 0).reshape(nf, 4, 3), want) < TOL_MAP, s
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 3, 3), (4, 3, 5, 4), (5, 4, 3, 6)], ids=["3^4", "4x3x5x4", "5x4x3x6"])
+def test_small_lattices_coinciding_hops(dims):
+    """At L = 3 the hops +2 and -1 (and -2 and +1) reach the same site and at L = 4 the hops +2 and -2
+    do; the layer must still be the plain sum over the 27 hops (both layouts, and the adjoint)."""
+    L = NetLattice(dims, eps=0.5, seed=120)
+    ok = L.ok
+    A = rand_A((27, 4, 4), 121)
+    for nf, inner in ((2, False), (5, True)):
+        phi = I.gaussian_sources(L.dims, nf, 122)
+        d_in = L.up(phi, inner)
+        out = L.torch.empty_like(d_in)
+        fl = ok.OK_SPINOR_RHS_INNER if inner else 0
+        ok.ok_net_layer(L.dims, L.params(A), L.T, d_in, out, nf, fl)
+        L.sync()
+        assert rel(L.down(out, nf, inner), N.layer(L.P, A, phi)) < TOL_MAP
+        ok.ok_net_layer(L.dims, L.params(A), L.T, d_in, out, nf, fl | ok.OK_NET_ADJOINT)
+        L.sync()
+        assert rel(L.down(out, nf, inner), N.layer_adjoint(L.P, A, phi)) < TOL_MAP
+
+
+@pytest.mark.parametrize("n_layers", [1, 2, 3, 16])
+def test_network_depths(nl, n_layers):
+    """One layer (no work buffer), two (one ping-pong field), three and sixteen (both alternate)."""
+    ok = nl.ok
+    params = I.net_init_params(n_layers, 0.7, 130 + n_layers, noise=0.05)
+    net = ok.Net(n_layers, nl.params(params), nl.T)
+    phi = I.gaussian_sources(nl.dims, 2, 131)
+    d_in = nl.up(phi)
+    out = nl.torch.empty_like(d_in)
+    nb = ok.ok_net_workspace_bytes(nl.dims, n_layers, 2, 0)
+    work = ok.empty_bytes(nb)
+    ok.ok_net_apply(nl.dims, net, d_in, out, 2, 0, work)
+    nl.sync()
+    assert rel(nl.down(out, 2), N.forward(nl.P, params, phi)[-1]) < 4 * TOL_MAP
+
+
+def test_gauge_covariance_on_gpu():
+    """The GPU network on gauge-transformed links and fields equals the transformed output."""
+    dims = (4, 5, 4, 6)
+    U = I.random_su3_links(dims, 0.4, 140)
+    g = I.random_su3_field(dims, 141)
+    ok = lib()
+    import torch
+    params = I.net_init_params(2, 0.6, 142, noise=0.1)
+    phi = I.gaussian_sources(dims, 1, 143)
+    from oracle.lattice import cmul
+    outs = []
+    for links, f in ((U, phi), (I.gauge_transform_links(U, g), cmul(g, phi))):
+        T = ok.empty_bytes(ok.ok_net_transports_bytes(dims))
+        ok.ok_net_transports(dims, ok.to_device_complex(links), T)
+        net = ok.Net(2, ok.to_device_complex(params, dtype="float32"), T)
+        d_in = ok.to_device_complex(f, dtype="float32")
+        out = torch.empty_like(d_in)
+        ok.ok_net_apply(dims, net, d_in, out, 1, 0, ok.empty_bytes(ok.ok_net_workspace_bytes(dims, 2, 1, 0)))
+        torch.cuda.synchronize()
+        outs.append(ok.to_host_complex(out, f.shape))
+    assert rel(outs[1], cmul(g, outs[0])) < 1e-5

@@ -328,3 +328,18 @@ def test_c2_full_size_mixed_vs_plain():
         print("C2 %s: %d iterations, %d reliable updates, |x - x64|/|x64| = %.2e"
               % ("f32" if low == ok.OK_F32 else "bf16", st[0]["iterations"], st[0]["reliable_updates"], err))
         assert err < 1e-8
+
+
+def test_batched_with_network_two_groups(c4small):
+    """20 right-hand sides (groups of 16 and 4) preconditioned by the network, one of them zero."""
+    ok = lib()
+    L = c4small
+    xi = I.gaussian_sources(L.dims, 20, 75)
+    xi[7] = 0.0
+    rc, st, x = solve(L, xi, low=ok.OK_BF16 | SITE, net=L.net)
+    assert rc == ok.OK_SUCCESS
+    assert np.all(x[7] == 0) and st[7]["iterations"] == 0
+    for k in range(20):
+        if k != 7:
+            assert st[k]["fallbacks"] == 0 and st[k]["net_applies"] > 0
+            assert oracle_resid(L.U, L.c, xi[k], x[k]) <= ORACLE_SLACK * TOL
