@@ -169,16 +169,16 @@ int launch_apply_t(const Geo& g, const void* W, const void* psi, void* out, doub
 }
 
 // FP64 W (plane layout) applied to NR right-hand sides in one pass, out_r = mhat in_r + sum_k W_k in_r(x+d_k):
-// each W element is loaded once and multiplied into every right-hand side.  Four threads per site
-// (three output rows each); the right-hand sides are separate FP64 fields [V][12] named in `cols`.
+// each W element is loaded once and multiplied into every right-hand side.  TPS threads per site
+// (12/TPS output rows each); the right-hand sides are separate FP64 fields [V][12] named in `cols`.
 struct Cols64 {
     const double* in[4];
     double* out[4];
 };
 
-template <int NR>
+template <int NR, int TPS>
 __global__ void __launch_bounds__(256) k_apply_m64(Geo g, const void* __restrict__ W, Cols64 cols, double mhat) {
-    constexpr int TPS = 4, RPT = 3, SPW = 16;
+    constexpr int RPT = 12 / TPS, SPW = 64 / TPS;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int grp = lane / SPW;
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256) k_apply_m64(Geo g, const void* __restrict
 #pragma unroll 1
     for (int k = 0; k < kW; ++k) {
         const int n = neighbour(g, x, y, z, t, off_d(k, 0), off_d(k, 1), off_d(k, 2), off_d(k, 3));
-#pragma unroll
+#pragma unroll 2
         for (int j = 0; j < 12; ++j) {
             c128 w[RPT];
 #pragma unroll
@@ -221,8 +221,12 @@ __global__ void __launch_bounds__(256) k_apply_m64(Geo g, const void* __restrict
 #pragma unroll
         for (int q = 0; q < RPT; ++q) o[q] = make_double2(acc[r][q].re, acc[r][q].im);
     }
-    (void)TPS;
 }
+
+#ifndef OKINV_M64_TPS
+#define OKINV_M64_TPS 4
+#endif
+constexpr int M64_TPS = OKINV_M64_TPS;
 
 }  // namespace
 
@@ -235,12 +239,12 @@ int launch_apply_m64(const Geo& g, const void* W, const double* const* in, doubl
             c.in[r] = in[r0 + r];
             c.out[r] = out[r0 + r];
         }
-        const unsigned nb = grid_for((long)g.V * 4, 256);
+        const unsigned nb = grid_for((long)g.V * M64_TPS, 256);
         switch (nr) {
-            case 1: k_apply_m64<1><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
-            case 2: k_apply_m64<2><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
-            case 3: k_apply_m64<3><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
-            default: k_apply_m64<4><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+            case 1: k_apply_m64<1, M64_TPS><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+            case 2: k_apply_m64<2, M64_TPS><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+            case 3: k_apply_m64<3, M64_TPS><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
+            default: k_apply_m64<4, M64_TPS><<<nb, 256, 0, st>>>(g, W, c, mhat); break;
         }
         OK_LAUNCH_CHECK("k_apply_m64");
     }
