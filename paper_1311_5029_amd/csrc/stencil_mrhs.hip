@@ -255,12 +255,15 @@ template <> struct Ops<OK_BF16> {
 // their lanes read a valid in-block address instead of being zeroed.
 template <int P, int SL> struct LaneOff {
     int a[3], a1, b[4];
+    bool wl, bl;   // FP32: this lane's W row / right-hand side is live (otherwise its operand is zero)
 };
 
 template <int P, int SL>
 __device__ __forceinline__ LaneOff<P, SL> lane_offsets(int l16, int grp, int nrhs, size_t V) {
     LaneOff<P, SL> o;
     const int j = l16 < nrhs ? l16 : nrhs - 1;
+    o.wl = l16 < 12;
+    o.bl = l16 < nrhs;
     if constexpr (P == OK_F32) {
         const int i = l16 < 12 ? l16 : l16 - 4;
 #pragma unroll
@@ -290,9 +293,9 @@ __device__ __forceinline__ void load_ops(Ops<P>& o, const uint4* __restrict__ wk
     if constexpr (P == OK_F32) {
         const float2* pa = reinterpret_cast<const float2*>(wk);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            o.a[q] = ld_stream(pa + lo.a[q]);
-            o.b[q] = SL ? sp[lo.b[q]] : sp[4 * q + grp];
+        for (int q = 0; q < 3; ++q) {   // padding rows and columns load nothing
+            o.a[q] = lo.wl ? ld_stream(pa + lo.a[q]) : make_float2(0.f, 0.f);
+            o.b[q] = lo.bl ? (SL ? sp[lo.b[q]] : sp[4 * q + grp]) : make_float2(0.f, 0.f);
         }
     } else {
 #pragma unroll
