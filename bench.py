@@ -211,13 +211,13 @@ def cpu_baseline():
 
 
 def learned(args):
-    """C4 / C5: the learned preconditioner, trained on the GPU on the same gauge field.
+    """The learned preconditioner, trained on the GPU on the same gauge field.
 
-    c4: 24^3x64, 256 training pairs, 64 fresh Gaussian evaluation sources; each solved
+    learned_24x24x24x64: 256 training pairs, 64 fresh Gaussian evaluation sources; each solved
         plain (FP64, unpreconditioned), mixed (FP32 W + FP64 reliable updates) with and without
         the network, and in batches of 16 (BF16 site-major W on the matrix cores) with and
         without the network.
-    c5: 32^3x64, 12 point sources: plain FP64 one after the other vs the network + batched BF16
+    learned_batched_32x32x32x64: 12 point sources: plain FP64 one after the other vs the network + batched BF16
         on the matrix cores (12 together); the network is trained on 64 Gaussian pairs.
     Training pairs come from the batched solver: FP64 solutions with true residual <= 1e-10,
     the same criterion the plain solver stops at."""
@@ -228,20 +228,20 @@ def learned(args):
     from paper_1311_5029_amd import train as TR
 
     torch.cuda.set_device(0)
-    c4 = args.workload == "c4"
-    dims = tuple(args.dims) if args.dims else ((24, 24, 24, 64) if c4 else (32, 32, 32, 64))
+    gauss_eval = args.workload == "learned_24x24x24x64"
+    dims = tuple(args.dims) if args.dims else ((24, 24, 24, 64) if gauss_eval else (32, 32, 32, 64))
     V = int(np.prod(dims))
-    n_train = args.n_train or (256 if c4 else 64)
-    n_eval = args.n_eval or (64 if c4 else 12)
+    n_train = args.n_train or (256 if gauss_eval else 64)
+    n_eval = args.n_eval or (64 if gauss_eval else 12)
     SITE = ok.OK_LAYOUT_SITE
     log("%s: links %s" % (args.workload, dims))
-    cfg = I.make_config("C4" if c4 else "C5", dims=dims, with_sources=False)
+    cfg = I.make_config(args.workload, dims=dims, with_sources=False)
     c = cfg["coeffs"]
     links = ok.to_device_complex(cfg["U"])
     del cfg["U"]
     Ws = {}
     pre = {}
-    for prec in ([ok.OK_F64, ok.OK_F32, ok.OK_BF16 | SITE] if c4 else [ok.OK_F64, ok.OK_BF16 | SITE]):
+    for prec in ([ok.OK_F64, ok.OK_F32, ok.OK_BF16 | SITE] if gauss_eval else [ok.OK_F64, ok.OK_BF16 | SITE]):
         Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(dims, prec))
         scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(dims))
         torch.cuda.synchronize()
@@ -260,7 +260,7 @@ def learned(args):
     torch.cuda.synchronize()
     t = time.perf_counter()
     net, hist = TR.train(dims, T, xi32, psi32, n_train, 1.0 / c.mhat, n_layers=4, steps=args.train_steps,
-                         batch=16 if c4 else 8, lr=3e-3, log=log)
+                         batch=16 if gauss_eval else 8, lr=3e-3, log=log)
     train_s = time.perf_counter() - t
     del xi32, psi32
     torch.cuda.empty_cache()
@@ -288,7 +288,7 @@ def learned(args):
         f["resid"].extend(s["true_rel_resid"] for s in st)
         f["fallbacks"] += sum(s["fallbacks"] for s in st)
 
-    if c4:
+    if gauss_eval:
         for j, xi in enumerate(I.gaussian_source_batches(dims, n_eval, I.SEED_EVAL, 16)):
             for k in range(xi.shape[0]):
                 for name, low, wn in (("plain_f64", None, False), ("mixed_f32", ok.OK_F32, False),
@@ -319,8 +319,8 @@ def learned(args):
     plain = summary["plain_f64"]["seconds_per_source"]
     out = {
         "metric": "time to 1e-10 residual per source, plain FP64 vs learned preconditioner",
-        "workload": "%s: %dx%dx%dx%d, plaquette 0.6 links, %d %s sources" % (
-            args.workload.upper(), *dims, n_eval if c4 else 12, "Gaussian evaluation" if c4 else "point"),
+        "workload": "%dx%dx%dx%d, plaquette 0.6 links, %d %s sources" % (
+            *dims, n_eval if gauss_eval else 12, "Gaussian evaluation" if gauss_eval else "point"),
         "n_gpus": 1, "unit": "s/source", "higher_is_better": False,
         "value": summary["batched_bf16_net"]["seconds_per_source"],
         "speedup_vs_plain": {k: round(plain / v["seconds_per_source"], 3) for k, v in summary.items()},
@@ -336,8 +336,8 @@ def learned(args):
     print(json.dumps(out), flush=True)
 
 
-def mixed_c2(args):
-    """C2: 16^3x32, plaquette 0.6, one Gaussian source: plain FP64 BiCGStab vs FP32 (and BF16) W with
+def mixed(args):
+    """16^3x32, plaquette 0.6, one Gaussian source: plain FP64 BiCGStab vs FP32 (and BF16) W with
     FP64 reliable updates, all to 1e-10; each mixed solution's error against the plain FP64 one."""
     import torch
 
@@ -346,7 +346,7 @@ def mixed_c2(args):
 
     torch.cuda.set_device(0)
     dims = tuple(args.dims) if args.dims else (16, 16, 16, 32)
-    cfg = I.make_config("C2", dims=dims)
+    cfg = I.make_config("mixed_16x16x16x32", dims=dims)
     c = cfg["coeffs"]
     links = ok.to_device_complex(cfg["U"])
     Ws = {}
@@ -357,7 +357,7 @@ def mixed_c2(args):
         del scr
     xi = ok.to_device_complex(cfg["xi"][0])
     out = {"metric": "time to 1e-10 residual, plain FP64 vs mixed precision with FP64 reliable updates",
-           "workload": "C2: %dx%dx%dx%d, plaquette 0.6 links, one Gaussian source" % dims, "n_gpus": 1,
+           "workload": "%dx%dx%dx%d, plaquette 0.6 links, one Gaussian source" % dims, "n_gpus": 1,
            "unit": "s", "forms": {}}
     sol = {}
     for name, low in (("plain_f64", None), ("mixed_f32", ok.OK_F32), ("mixed_bf16", ok.OK_BF16)):
@@ -459,9 +459,12 @@ def main():
                     help="summarise two rocprofv3 --pmc runs into the traffic file and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 --kernel-trace --stats run and exit")
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "net"],
-                    help="c3 (default): the M.psi bench line; c2: plain vs mixed precision; "
-                         "c4/c5: learned-preconditioner solves; net: the network kernels alone")
+    ap.add_argument("--workload", default="batched_20x20x20x64",
+                    choices=["batched_20x20x20x64", "mixed_16x16x16x32", "learned_24x24x24x64",
+                             "learned_batched_32x32x32x64", "net"],
+                    help="batched_20x20x20x64 (default): the M.psi bench line and its solves; "
+                         "mixed_16x16x16x32: plain vs mixed precision; learned_*: learned-preconditioner "
+                         "solves; net: the network kernels alone")
     ap.add_argument("--dims", type=int, nargs=4, help="override the c4/c5 lattice (Lx Ly Lz Lt)")
     ap.add_argument("--n-train", type=int, default=0)
     ap.add_argument("--n-eval", type=int, default=0)
@@ -474,16 +477,16 @@ def main():
         parse_pmc(args.parse_pmc[0], args.parse_pmc[1], args.form)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d refused)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "net":
         net_kernels(args)
         return
-    if args.workload == "c2":
-        mixed_c2(args)
+    if args.workload == "mixed_16x16x16x32":
+        mixed(args)
         return
-    if args.workload != "c3":
+    if args.workload.startswith("learned"):
         learned(args)
         return
 
@@ -496,7 +499,7 @@ def main():
     form = {"f64": ok.OK_F64, "f32": ok.OK_F32, "bf16": ok.OK_BF16}[args.form]
     log("generating links 20^3x64")
     t0 = time.time()
-    cfg = I.make_config("C3")
+    cfg = I.make_config("batched_20x20x20x64")
     c = cfg["coeffs"]
     log("links in %.1fs, plaquette^(1/4) = u0 = %.5f, eps = %.5f" % (time.time() - t0, cfg["u0"], cfg["eps"]))
     links = ok.to_device_complex(cfg["U"])

@@ -234,13 +234,15 @@ def wilson_clover_coeffs(m0=0.1):
                           c_EE=0.0, c_1=0.0, c_2=0.0, c_3=0.0, c_4=0.0, c_5=0.0)
 
 
-# The five synthetic workloads: lattice, link roughness, sources.
+# The five synthetic workloads: lattice, link roughness, sources; `seed` picks the link
+# stream (1000 + seed) and the source stream (2000 + seed).
 CONFIGS = {
-    "C1": dict(dims=(4, 4, 4, 4), eps=0.3, nrhs=1, sources="gaussian"),
-    "C2": dict(dims=(16, 16, 16, 32), eps="plaq0.6", nrhs=1, sources="gaussian"),
-    "C3": dict(dims=(20, 20, 20, 64), eps="plaq0.6", nrhs=12, sources="point"),
-    "C4": dict(dims=(24, 24, 24, 64), eps="plaq0.6", nrhs=64, sources="gaussian"),
-    "C5": dict(dims=(32, 32, 32, 64), eps="plaq0.6", nrhs=12, sources="point"),
+    "dense_4x4x4x4": dict(seed=1, dims=(4, 4, 4, 4), eps=0.3, nrhs=1, sources="gaussian"),
+    "mixed_16x16x16x32": dict(seed=2, dims=(16, 16, 16, 32), eps="plaq0.6", nrhs=1, sources="gaussian"),
+    "batched_20x20x20x64": dict(seed=3, dims=(20, 20, 20, 64), eps="plaq0.6", nrhs=12, sources="point"),
+    "learned_24x24x24x64": dict(seed=4, dims=(24, 24, 24, 64), eps="plaq0.6", nrhs=64, sources="gaussian"),
+    "learned_batched_32x32x32x64": dict(seed=5, dims=(32, 32, 32, 64), eps="plaq0.6", nrhs=12,
+                                        sources="point"),
 }
 
 _EPS_CACHE = {}
@@ -259,7 +261,7 @@ def make_config(name, dims=None, with_sources=True):
     (optionally at other dims)."""
     cfg = CONFIGS[name]
     d = tuple(dims) if dims is not None else cfg["dims"]
-    num = int(name[1:])
+    num = cfg["seed"]
     eps = config_epsilon(cfg["eps"])
     U = random_su3_links(d, eps, SEED_LINKS + num)
     u0 = tadpole_u0(U)

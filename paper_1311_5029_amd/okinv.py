@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libokinv.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libokinv.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    raise ImportError("libokinv.so is not built (%s); build it with python -m paper_1311_5029_amd.build" % LIB_PATH)
 _lib = C.CDLL(LIB_PATH)
 
 OK_F64, OK_F32, OK_BF16 = 0, 1, 2

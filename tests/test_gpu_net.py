@@ -1,4 +1,4 @@
-"""GPU learned-preconditioner kernels judged by the FP64 network oracle.
+"""GPU learned-preconditioner kernels checked against the FP64 network oracle.
 
 Forward and adjoint layers, weight gradients, the loss and its gradient, the
 whole network, Adam and the training step, in both field layouts ([nf][V][12]

@@ -211,7 +211,7 @@ def test_free_field_plane_wave_f64():
 def big():
     ok = lib()
     dims = (20, 20, 20, 64)
-    cfg = I.make_config("C3")
+    cfg = I.make_config("batched_20x20x20x64")
     L = Lattice(dims, cfg["U"], cfg["coeffs"])
     L.precompute(ok.OK_F32)
     L.precompute(ok.OK_F64)

@@ -1,7 +1,7 @@
-"""GPU BiCGStab (ok_bicgstab) judged by the FP64 oracle.
+"""GPU BiCGStab (ok_bicgstab) checked against the FP64 oracle.
 
-Several solutions are correct (any psi with small enough residual), so the judge
-is the true residual ||xi - M psi|| / ||xi|| computed with the oracle's M; psi is
+Several solutions are correct (any psi with small enough residual), so the test
+criterion is the true residual ||xi - M psi|| / ||xi|| computed with the oracle's M; psi is
 compared directly only where an exact solution exists (dense LU on 4^4, the FFT
 point-source solution of a pure-gauge field), within kappa(M) times the tolerance.
 """
@@ -47,7 +47,7 @@ def oracle_resid(U, c, xi, x):
 
 
 @pytest.fixture(scope="module")
-def c1():
+def small():
     dims = (4, 4, 4, 4)
     U = I.random_su3_links(dims, 0.3, I.SEED_LINKS + 1)
     c = I.standin_coeffs(m0=0.5, u0=I.tadpole_u0(U))
@@ -61,58 +61,58 @@ def c1():
     return L
 
 
-def test_c1_plain_matches_dense_lu(c1):
+def test_4x4x4x4_plain_matches_dense_lu(small):
     ok = lib()
-    rc, st, x = solve(c1, c1.xi)
+    rc, st, x = solve(small, small.xi)
     assert rc == ok.OK_SUCCESS and st[0]["status"] == 0
     assert st[0]["true_rel_resid"] <= TOL
-    assert oracle_resid(c1.U, c1.c, c1.xi, x) <= ORACLE_SLACK * TOL
-    err = np.linalg.norm(x - c1.x_lu) / np.linalg.norm(c1.x_lu)
-    assert err <= c1.kappa * TOL
+    assert oracle_resid(small.U, small.c, small.xi, x) <= ORACLE_SLACK * TOL
+    err = np.linalg.norm(x - small.x_lu) / np.linalg.norm(small.x_lu)
+    assert err <= small.kappa * TOL
 
 
 @pytest.mark.parametrize("low", [1, 2], ids=["f32", "bf16"])
-def test_c1_mixed_precision(c1, low):
+def test_4x4x4x4_mixed_precision(small, low):
     ok = lib()
-    rc, st, x = solve(c1, c1.xi, low=low)
+    rc, st, x = solve(small, small.xi, low=low)
     assert rc == ok.OK_SUCCESS
     assert st[0]["reliable_updates"] >= 1 and st[0]["matvec_lo"] > 0
-    assert oracle_resid(c1.U, c1.c, c1.xi, x) <= ORACLE_SLACK * TOL
-    err = np.linalg.norm(x - c1.x_lu) / np.linalg.norm(c1.x_lu)
-    assert err <= c1.kappa * TOL
+    assert oracle_resid(small.U, small.c, small.xi, x) <= ORACLE_SLACK * TOL
+    err = np.linalg.norm(x - small.x_lu) / np.linalg.norm(small.x_lu)
+    assert err <= small.kappa * TOL
 
 
-def test_zero_source_gives_zero(c1):
+def test_zero_source_gives_zero(small):
     ok = lib()
-    rc, st, x = solve(c1, np.zeros_like(c1.xi))
+    rc, st, x = solve(small, np.zeros_like(small.xi))
     assert rc == ok.OK_SUCCESS and st[0]["iterations"] == 0 and np.all(x == 0)
 
 
-def test_nonfinite_source_rejected(c1):
+def test_nonfinite_source_rejected(small):
     ok = lib()
-    xi = c1.xi.copy()
+    xi = small.xi.copy()
     xi[1, 2, 3, 0, 2, 1] = np.nan
     with pytest.raises(ok.OkError) as e:
-        solve(c1, xi)
+        solve(small, xi)
     assert e.value.status == ok.OK_ENONFINITE
 
 
-def test_max_iter_reports_not_converged(c1):
+def test_max_iter_reports_not_converged(small):
     ok = lib()
-    rc, st, x = solve(c1, c1.xi, params=ok.SolverParams(tol=TOL, max_iter=1))
+    rc, st, x = solve(small, small.xi, params=ok.SolverParams(tol=TOL, max_iter=1))
     assert rc == ok.OK_NOT_CONVERGED and st[0]["status"] == ok.OK_NOT_CONVERGED
     assert st[0]["iterations"] == 1 and st[0]["true_rel_resid"] > TOL
 
 
-def test_guess_is_used(c1):
+def test_guess_is_used(small):
     ok = lib()
-    rc, st, x = solve(c1, c1.xi, guess=c1.x_lu)
+    rc, st, x = solve(small, small.xi, guess=small.x_lu)
     assert rc == ok.OK_SUCCESS and st[0]["iterations"] <= 1
 
 
-def test_solve_deterministic(c1):
-    _, _, a = solve(c1, c1.xi)
-    _, _, b = solve(c1, c1.xi)
+def test_solve_deterministic(small):
+    _, _, a = solve(small, small.xi)
+    _, _, b = solve(small, small.xi)
     assert np.array_equal(a, b)
 
 
@@ -131,10 +131,10 @@ def test_multiple_rhs_and_ragged_lattice():
 
 
 def test_plaquette06_mixed_vs_plain():
-    """8^3 x 16 at plaquette ~ 0.6 (the C2 link ensemble at a smaller volume)."""
+    """8^3 x 16 at plaquette ~ 0.6 (the 16^3 x 32 link ensemble at a smaller volume)."""
     ok = lib()
     dims = (8, 8, 8, 16)
-    cfg = I.make_config("C2", dims=dims)
+    cfg = I.make_config("mixed_16x16x16x32", dims=dims)
     L = Lattice(dims, cfg["U"], cfg["coeffs"])
     xi = cfg["xi"][0]
     rc64, st64, x64 = solve(L, xi)
@@ -164,14 +164,14 @@ SITE = 0x10
 
 
 @pytest.mark.parametrize("low", [1, 2], ids=["f32", "bf16"])
-def test_batched_c1_twelve_sources(c1, low):
+def test_batched_4x4x4x4_twelve_sources(small, low):
     ok = lib()
-    xi = I.gaussian_sources(c1.dims, 12, 71)
-    rc, st, x = solve(c1, xi, low=low | SITE)
+    xi = I.gaussian_sources(small.dims, 12, 71)
+    rc, st, x = solve(small, xi, low=low | SITE)
     assert rc == ok.OK_SUCCESS and len(st) == 12
     for k in range(12):
         assert st[k]["status"] == 0 and st[k]["reliable_updates"] >= 1
-        assert oracle_resid(c1.U, c1.c, xi[k], x[k]) <= ORACLE_SLACK * TOL
+        assert oracle_resid(small.U, small.c, xi[k], x[k]) <= ORACLE_SLACK * TOL
 
 
 def test_batched_zero_source_and_groups_of_16():
@@ -191,19 +191,19 @@ def test_batched_zero_source_and_groups_of_16():
             assert oracle_resid(U, c, xi[k], x[k]) <= ORACLE_SLACK * TOL
 
 
-def test_batched_max_iter_not_converged(c1):
+def test_batched_max_iter_not_converged(small):
     ok = lib()
-    xi = I.gaussian_sources(c1.dims, 4, 73)
-    rc, st, x = solve(c1, xi, low=ok.OK_F32 | SITE, params=ok.SolverParams(tol=TOL, max_iter=2))
+    xi = I.gaussian_sources(small.dims, 4, 73)
+    rc, st, x = solve(small, xi, low=ok.OK_F32 | SITE, params=ok.SolverParams(tol=TOL, max_iter=2))
     assert rc == ok.OK_NOT_CONVERGED
     assert all(s["status"] == ok.OK_NOT_CONVERGED and s["iterations"] == 2 for s in st)
 
 
-def test_batched_deterministic(c1):
+def test_batched_deterministic(small):
     ok = lib()
-    xi = I.gaussian_sources(c1.dims, 12, 74)
-    _, _, a = solve(c1, xi, low=ok.OK_BF16 | SITE)
-    _, _, b = solve(c1, xi, low=ok.OK_BF16 | SITE)
+    xi = I.gaussian_sources(small.dims, 12, 74)
+    _, _, a = solve(small, xi, low=ok.OK_BF16 | SITE)
+    _, _, b = solve(small, xi, low=ok.OK_BF16 | SITE)
     assert np.array_equal(a, b)
 
 
@@ -222,10 +222,10 @@ def test_batched_pure_gauge_point_sources_fft():
 
 
 def test_batched_plaquette06_point_sources():
-    """The C3 link ensemble and point sources at a reduced 8^3 x 16 volume."""
+    """The 20^3 x 64 link ensemble and point sources at a reduced 8^3 x 16 volume."""
     ok = lib()
     dims = (8, 8, 8, 16)
-    cfg = I.make_config("C3", dims=dims)
+    cfg = I.make_config("batched_20x20x20x64", dims=dims)
     L = Lattice(dims, cfg["U"], cfg["coeffs"])
     xi = cfg["xi"]
     rc, st, x = solve(L, xi, low=ok.OK_BF16 | SITE)
@@ -236,12 +236,12 @@ def test_batched_plaquette06_point_sources():
 
 # --- right preconditioning by the learned network ---------------------------------------------
 @pytest.fixture(scope="module")
-def c4small():
-    """The C4 link ensemble at 8^3 x 8, with a network trained on 16 GPU-solved pairs."""
+def learned_small():
+    """The 24^3 x 64 link ensemble at 8^3 x 8, with a network trained on 16 GPU-solved pairs."""
     from gpu_util import train_net
     ok = lib()
     dims = (8, 8, 8, 8)
-    cfg = I.make_config("C4", dims=dims)
+    cfg = I.make_config("learned_24x24x24x64", dims=dims)
     L = Lattice(dims, cfg["U"], cfg["coeffs"])
     xi = I.gaussian_sources(dims, 16, I.SEED_TRAIN)
     rc, st, psi = solve(L, xi, low=ok.OK_BF16 | SITE)
@@ -252,9 +252,9 @@ def c4small():
     return L
 
 
-def test_trained_network_cuts_iterations(c4small):
+def test_trained_network_cuts_iterations(learned_small):
     ok = lib()
-    L = c4small
+    L = learned_small
     assert L.loss < 0.3
     for k in range(2):
         xi = L.xi_eval[k]
@@ -267,9 +267,9 @@ def test_trained_network_cuts_iterations(c4small):
 
 
 @pytest.mark.parametrize("low", [1, 2], ids=["f32", "bf16"])
-def test_batched_with_network(c4small, low):
+def test_batched_with_network(learned_small, low):
     ok = lib()
-    L = c4small
+    L = learned_small
     rc0, st0, _ = solve(L, L.xi_eval, low=low | SITE)
     rc1, st1, x = solve(L, L.xi_eval, low=low | SITE, net=L.net)
     assert rc0 == rc1 == ok.OK_SUCCESS
@@ -281,11 +281,11 @@ def test_batched_with_network(c4small, low):
 
 @pytest.mark.parametrize("bad", ["zero", "nan"])
 @pytest.mark.parametrize("low", [1, 1 | 0x10], ids=["single", "batched"])
-def test_failing_network_falls_back(c4small, bad, low):
+def test_failing_network_falls_back(learned_small, bad, low):
     """A zero network breaks the recurrence down at once (v = M N p = 0); a NaN network makes it
     non-finite.  Either way the unpreconditioned solve takes over and converges."""
     ok = lib()
-    L = c4small
+    L = learned_small
     torch = L.torch
     n = ok.ok_net_param_count(2)
     p = torch.zeros(n, dtype=torch.float32, device="cuda")
@@ -302,19 +302,19 @@ def test_failing_network_falls_back(c4small, bad, low):
         assert oracle_resid(L.U, L.c, xis[k], xs[k]) <= ORACLE_SLACK * TOL
 
 
-def test_network_needs_low_precision_solve(c4small):
+def test_network_needs_low_precision_solve(learned_small):
     ok = lib()
     with pytest.raises(ok.OkError) as e:
-        solve(c4small, c4small.xi_eval[0], net=c4small.net)
+        solve(learned_small, learned_small.xi_eval[0], net=learned_small.net)
     assert e.value.status == ok.OK_EINVAL
 
 
-def test_c2_full_size_mixed_vs_plain():
-    """The C2 workload at its size (16^3 x 32, plaquette 0.6, one Gaussian source): plain FP64 and
+def test_16x16x16x32_mixed_vs_plain_full_size():
+    """The 16^3 x 32 mixed-precision workload at its size (plaquette 0.6, one Gaussian source): plain FP64 and
     FP32 / BF16 W with FP64 reliable updates all reach the oracle's residual bound, and the mixed
     solutions agree with the plain FP64 one to within the conditioning times the tolerance."""
     ok = lib()
-    cfg = I.make_config("C2")
+    cfg = I.make_config("mixed_16x16x16x32")
     L = Lattice(cfg["dims"], cfg["U"], cfg["coeffs"])
     xi = cfg["xi"][0]
     rc, st, x64 = solve(L, xi)
@@ -325,15 +325,15 @@ def test_c2_full_size_mixed_vs_plain():
         assert rc == ok.OK_SUCCESS and st[0]["reliable_updates"] >= 1
         assert oracle_resid(cfg["U"], cfg["coeffs"], xi, x) <= ORACLE_SLACK * TOL
         err = np.linalg.norm(x - x64) / np.linalg.norm(x64)
-        print("C2 %s: %d iterations, %d reliable updates, |x - x64|/|x64| = %.2e"
+        print("16^3x32 %s: %d iterations, %d reliable updates, |x - x64|/|x64| = %.2e"
               % ("f32" if low == ok.OK_F32 else "bf16", st[0]["iterations"], st[0]["reliable_updates"], err))
         assert err < 1e-8
 
 
-def test_batched_with_network_two_groups(c4small):
+def test_batched_with_network_two_groups(learned_small):
     """20 right-hand sides (groups of 16 and 4) preconditioned by the network, one of them zero."""
     ok = lib()
-    L = c4small
+    L = learned_small
     xi = I.gaussian_sources(L.dims, 20, 75)
     xi[7] = 0.0
     rc, st, x = solve(L, xi, low=ok.OK_BF16 | SITE, net=L.net)

@@ -389,7 +389,7 @@ def test_translation_invariance(rough):
 
 # --- P11 dense brute force ----------------------------------------------------
 def test_dense_lu_vs_bicgstab_c1():
-    """Config C1: 4^4, eps = 0.3, u0 from the plaquette, Gaussian source."""
+    """The 4^4 workload: eps = 0.3, u0 from the plaquette, Gaussian source."""
     U = I.random_su3_links(D4, 0.3, I.SEED_LINKS + 1)
     c = all_on(u0=I.tadpole_u0(U))
     M = dense_from_W(WForm(U, c).W, c.mhat, D4, offsets())
