@@ -36,6 +36,8 @@ NRHS = 12
 # algorithmic bytes per site of one single-right-hand-side application: dense
 # 27 x 12x12 complex W + spinor in + spinor out
 BYTES_SITE = {0: 27 * 144 * 16 + 2 * 192, 1: 27 * 144 * 8 + 2 * 96, 2: 27 * 144 * 4 + 2 * 96}
+# the 14-block saved set (OK_LAYOUT_SAVED): each stored block read once from HBM
+BYTES_SAVED = {0: 14 * 144 * 16 + 2 * 192, 1: 14 * 144 * 8 + 2 * 96, 2: 14 * 144 * 4 + 2 * 96}
 # ... and of one application to the 12-RHS batch by the MFMA kernel: W streamed
 # once for all right-hand sides + 12 spinors in and out (FP64 W: 12 single launches)
 BYTES_STEP = {0: NRHS * BYTES_SITE[0], 1: 27 * 144 * 8 + NRHS * 2 * 96, 2: 27 * 144 * 4 + NRHS * 2 * 96}
@@ -506,7 +508,9 @@ def main():
     SITE, INNER = ok.OK_LAYOUT_SITE, ok.OK_SPINOR_RHS_INNER
     Ws = {}
     pre_ms = {}
-    wforms = [ok.OK_F64, ok.OK_F32, ok.OK_BF16, ok.OK_F32 | SITE, ok.OK_BF16 | SITE]
+    SAVED = ok.OK_LAYOUT_SAVED
+    wforms = [ok.OK_F64, ok.OK_F32, ok.OK_BF16, ok.OK_F32 | SITE, ok.OK_BF16 | SITE,
+              ok.OK_F64 | SAVED, ok.OK_F32 | SAVED, ok.OK_BF16 | SAVED]
     for prec in wforms:
         Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(DIMS, prec))
         scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(DIMS))
@@ -515,7 +519,8 @@ def main():
         ok.ok_precompute_W(DIMS, c, links, prec, Ws[prec], scr)
         e1.record()
         torch.cuda.synchronize()
-        pre_ms[PREC_NAME[prec & 3] + ("_site" if prec & SITE else "")] = round(e0.elapsed_time(e1), 3)
+        pre_ms[PREC_NAME[prec & 3] + ("_site" if prec & SITE else "_saved" if prec & SAVED else "")] = \
+            round(e0.elapsed_time(e1), 3)
         del scr
     log("precompute ms %s" % pre_ms)
 
@@ -566,11 +571,15 @@ def main():
     # context: one right-hand side (plane W), and the batched forms
     apply_forms = {}
     for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
-        ms = time_apply(prec, ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32, 1)
-        gbs = BYTES_SITE[prec] * V / (ms * 1e-3) / 1e9
-        apply_forms["1rhs_" + PREC_NAME[prec]] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
-                                                  "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                                  "rhs_sites_per_s": round(V / (ms * 1e-3), 0)}
+        for lay in (0, SAVED):
+            ms = time_apply(prec | lay, ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32, 1)
+            # the saved layout streams 14 of the 27 blocks per site (the other 13 are reread from
+            # neighbours); its GB/s counts the bytes of the layout it reads once
+            by = BYTES_SAVED[prec] if lay else BYTES_SITE[prec]
+            gbs = by * V / (ms * 1e-3) / 1e9
+            apply_forms["1rhs_" + PREC_NAME[prec] + ("_saved" if lay else "")] = {
+                "ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "rhs_sites_per_s": round(V / (ms * 1e-3), 0)}
     for prec in (ok.OK_F32, ok.OK_BF16):
         ms = time_apply(prec | SITE, ok.OK_F32 | INNER, NRHS)
         gbs = BYTES_STEP[prec] * V / (ms * 1e-3) / 1e9

@@ -67,6 +67,16 @@ enum ok_prec { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2 };
  * with OK_F32 and OK_BF16. */
 #define OK_LAYOUT_SITE 0x10
 
+/* Layout flag OR-ed into the W precision (OK_F64, OK_F32 or OK_BF16) of
+ * ok_W_bytes, ok_precompute_W, ok_apply_M and ok_W_to_dense: only the 14
+ * blocks of the forward offsets (k = 0, +mu, +2i, +i+j, +i-j: the saved set of
+ * Eq. FinalForm) are stored, plane-major; each backward block is formed where
+ * it is used from the neighbour's forward block by Eq. conjugate,
+ * W_{-d,x} = gamma5 W_{+d,x-d}^dag gamma5.  About half the bytes of the
+ * 27-block layout for the same numbers (one right-hand side at a time; not
+ * with OK_LAYOUT_SITE). */
+#define OK_LAYOUT_SAVED 0x100
+
 /* Spinor layout flag OR-ed into spinor_prec of ok_apply_M (FP32 spinors,
  * site-major W, nrhs <= 16): spinors stored [V][4][3][nrhs] complex, the
  * right-hand side index fastest, which the multi-right-hand-side kernel reads

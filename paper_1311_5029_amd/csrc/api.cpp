@@ -82,9 +82,10 @@ static int check_coeffs(const ok_coeffs* c) {
 
 static bool valid_prec(int p) { return p == OK_F64 || p == OK_F32 || p == OK_BF16; }
 
-// W precision with an optional OK_LAYOUT_SITE flag (FP32 and BF16 only)
+// W precision with an optional layout flag: OK_LAYOUT_SITE (FP32 and BF16) or OK_LAYOUT_SAVED
 static bool valid_wprec(int p) {
-    const int b = p & ~OK_LAYOUT_SITE;
+    const int b = p & ~(OK_LAYOUT_SITE | OK_LAYOUT_SAVED);
+    if ((p & OK_LAYOUT_SITE) && (p & OK_LAYOUT_SAVED)) return false;
     if (p & OK_LAYOUT_SITE) return b == OK_F32 || b == OK_BF16;
     return valid_prec(b);
 }
@@ -123,7 +124,7 @@ int ok_W_bytes(const ok_geom* g, int prec, size_t* bytes) {
         set_error("bytes is NULL");
         return OK_EINVAL;
     }
-    *bytes = w_bytes(prec & ~OK_LAYOUT_SITE, G.Vs);
+    *bytes = w_bytes(prec & 3, G.Vs, layout_of(prec));
     return OK_SUCCESS;
 }
 
@@ -147,7 +148,7 @@ int ok_precompute_W(const ok_geom* g, const ok_coeffs* c, const double* d_links,
         set_error("unknown W precision/layout %d", prec);
         return OK_EINVAL;
     }
-    const size_t wb = w_bytes(prec & ~OK_LAYOUT_SITE, G.Vs);
+    const size_t wb = w_bytes(prec & 3, G.Vs, layout_of(prec));
     OK_TRY(check_ptr(d_links, "d_links"));
     OK_TRY(check_ptr(d_W, "d_W"));
     OK_TRY(check_ptr(d_scratch, "d_scratch"));
@@ -197,8 +198,9 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
         set_error("unknown W precision/layout %d", W_prec);
         return OK_EINVAL;
     }
-    const int wbase = W_prec & ~OK_LAYOUT_SITE;
+    const int wbase = W_prec & 3;
     const bool site_major = (W_prec & OK_LAYOUT_SITE) != 0;
+    const bool saved = (W_prec & OK_LAYOUT_SAVED) != 0;
     const bool rhs_inner = (spinor_prec & OK_SPINOR_RHS_INNER) != 0;
     if (rhs_inner && (!site_major || nrhs > 16)) {
         set_error("OK_SPINOR_RHS_INNER needs site-major W (OK_LAYOUT_SITE) and nrhs <= 16");
@@ -227,10 +229,10 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
     if (site_major)
         return launch_apply_site(G, d_W, wbase, reinterpret_cast<const float*>(d_psi),
                                  reinterpret_cast<float*>(d_out), c->mhat, nrhs, rhs_inner ? 1 : 0, st);
-    if (nrhs > 1 && W_prec != OK_F64 && use_mrhs())
+    if (nrhs > 1 && wbase != OK_F64 && !saved && use_mrhs())
         return launch_apply_mrhs(G, d_W, W_prec, reinterpret_cast<const float*>(d_psi),
                                  reinterpret_cast<float*>(d_out), c->mhat, nrhs, st);
-    const int tps = stencil_tps(W_prec);
+    const int tps = saved ? 1 : stencil_tps(W_prec);
     for (int r = 0; r < nrhs; ++r) {
         const char* in = reinterpret_cast<const char*>(d_psi) + sb * r;
         char* out = reinterpret_cast<char*>(d_out) + sb * r;

@@ -458,6 +458,24 @@ __global__ void __launch_bounds__(64) k_to_dense(Geo g, const void* W, int layou
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     const int k = blockIdx.y, row = blockIdx.z;
+    if (layout == LAY_SAVED && saved_index(k) < 0) {
+        // backward block of the saved set: gamma5 (forward block at x - d)^dag gamma5
+        int kf = 0;
+        for (int i = 0; i < 13; ++i)
+            if (kBwd[i] == k) kf = kFwdOf[i];
+        int x, y, z, t;
+        site_coords(g, s, x, y, z, t);
+        const int src = neighbour(g, x, y, z, t, -off_d(kf, 0), -off_d(kf, 1), -off_d(kf, 2), -off_d(kf, 3));
+        const int al = row / 3, a = row % 3, alp = al ^ 2;
+        for (int be = 0; be < 4; ++be) {
+            const double sg = ((al < 2) == (be < 2)) ? 1.0 : -1.0;
+            for (int b = 0; b < 3; ++b) {
+                const c128 xv = w_load_entry<P>(W, g.Vs, layout, kf, (3 * (be ^ 2) + b) * 12 + 3 * alp + a, src);
+                dense[((size_t)s * kW + k) * kWE + row * 12 + 3 * be + b] = make_double2(sg * xv.re, -sg * xv.im);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int col = 0; col < 12; ++col) {
         c128 v = w_load_entry<P>(W, g.Vs, layout, k, row * 12 + col, s);
@@ -473,8 +491,10 @@ int run_precompute(const Geo& g, const PreCoef& q, const double* links, void* W,
     OK_LAUNCH_CHECK("k_clover");
     k_forward<P><<<dim3(nb, 14, 3), 64, 0, st>>>(g, q, links, F, W, layout);
     OK_LAUNCH_CHECK("k_forward");
-    k_backward<P><<<dim3(nb, 13, 12), 64, 0, st>>>(g, W, layout);
-    OK_LAUNCH_CHECK("k_backward");
+    if (layout != LAY_SAVED) {   // the saved set forms its backward blocks where they are used
+        k_backward<P><<<dim3(nb, 13, 12), 64, 0, st>>>(g, W, layout);
+        OK_LAUNCH_CHECK("k_backward");
+    }
     return OK_SUCCESS;
 }
 
@@ -497,8 +517,8 @@ int launch_precompute(const Geo& g, const ok_coeffs& c, const double* links, int
     q.cSii = (c.c_1 + 2.0 * c.c_2) * 0.5 / u0;
     q.cOff = c.c_2 * 0.5 / u0;
     double2* F = reinterpret_cast<double2*>(scratch);
-    const int layout = (prec & OK_LAYOUT_SITE) ? 1 : 0;
-    switch (prec & ~OK_LAYOUT_SITE) {
+    const int layout = layout_of(prec);
+    switch (prec & 3) {
         case OK_F64: return run_precompute<OK_F64>(g, q, links, W, layout, F, st);
         case OK_F32: return run_precompute<OK_F32>(g, q, links, W, layout, F, st);
         default: return run_precompute<OK_BF16>(g, q, links, W, layout, F, st);
@@ -508,8 +528,8 @@ int launch_precompute(const Geo& g, const ok_coeffs& c, const double* links, int
 int launch_to_dense(const Geo& g, const void* W, int prec, double* dense, hipStream_t st) {
     dim3 grid(grid_for(g.V, 64), kW, 12);
     double2* d = reinterpret_cast<double2*>(dense);
-    const int layout = (prec & OK_LAYOUT_SITE) ? 1 : 0;
-    switch (prec & ~OK_LAYOUT_SITE) {
+    const int layout = layout_of(prec);
+    switch (prec & 3) {
         case OK_F64: k_to_dense<OK_F64><<<grid, 64, 0, st>>>(g, W, layout, d); break;
         case OK_F32: k_to_dense<OK_F32><<<grid, 64, 0, st>>>(g, W, layout, d); break;
         default: k_to_dense<OK_BF16><<<grid, 64, 0, st>>>(g, W, layout, d); break;

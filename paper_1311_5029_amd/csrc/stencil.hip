@@ -168,6 +168,132 @@ int launch_apply_t(const Geo& g, const void* W, const void* psi, void* out, doub
     return OK_SUCCESS;
 }
 
+// Saved-set W (OK_LAYOUT_SAVED, 14 blocks per site): one thread per site owns all 12 output
+// rows.  A forward offset reads its block at x; the backward offset -d reads the forward block
+// X of +d at x - d (the site its spinor comes from) and applies gamma5 X^dag gamma5 on the fly.
+// Walking X row by row (the rows are what the plane layout stores contiguously per chunk):
+//   out_{(q+6)%12} += sg(p, q) conj(X[p][q]) v_{(p+6)%12},  sg = +1 if (p < 6) == (q < 6) else -1,
+// which is entry ((q+6)%12, (p+6)%12) of gamma5 X^dag gamma5 (gamma5 swaps the upper and lower
+// spin pairs, with a sign on the off-diagonal pair blocks).
+template <int P, typename T>
+__device__ __forceinline__ void saved_row_chunks(const void* __restrict__ W, int Vs, int ks, int row, int s,
+                                                 cpx<T> w[12]) {
+    constexpr int per = WL<P>::per, ch = WL<P>::chunks;
+#pragma unroll
+    for (int j = 0; j < 12 / per; ++j) {
+        const size_t cell = ((size_t)(ks * ch + row * (12 / per) + j)) * Vs + s;
+        if constexpr (P == OK_F64) {
+            const double2 d = ld_stream(reinterpret_cast<const double2*>(W) + cell);
+            w[j] = cpx<T>{d.x, d.y};
+        } else if constexpr (P == OK_F32) {
+            const float4 f = ld_stream(reinterpret_cast<const float4*>(W) + cell);
+            w[2 * j] = cpx<T>{f.x, f.y};
+            w[2 * j + 1] = cpx<T>{f.z, f.w};
+        } else {
+            const uint4 u4 = ld_stream(reinterpret_cast<const uint4*>(W) + cell);
+            const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[4 * j + e] = cpx<T>{bf16_to_f32(u[e] & 0xffffu), bf16_to_f32(u[e] >> 16)};
+        }
+    }
+}
+
+template <int P, int EPI>
+__global__ void __launch_bounds__(256) k_apply_saved(Geo g, const void* __restrict__ W,
+                                                     const typename Arith<P>::T* __restrict__ psi,
+                                                     typename Arith<P>::T* __restrict__ out, double mhat_d,
+                                                     const typename Arith<P>::T* __restrict__ aux,
+                                                     double2* __restrict__ partial) {
+    using T = typename Arith<P>::T;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = s < g.V;
+    double2 d1{0.0, 0.0}, d2{0.0, 0.0};
+    if (live) {
+        const T mhat = (T)mhat_d;
+        int x, y, z, t;
+        site_coords(g, s, x, y, z, t);
+        cpx<T> acc[12], v[12], w[12];
+        {
+            const cpx<T>* c = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) acc[q] = mhat * c[q];
+        }
+#pragma unroll 1
+        for (int ks = 0; ks < kSaved; ++ks) {   // forward offsets: W_k(x) psi(x + d_k)
+            const int k = saved_k(ks);
+            const int n = neighbour(g, x, y, z, t, off_d(k, 0), off_d(k, 1), off_d(k, 2), off_d(k, 3));
+            ld_spinor(psi, n, v);
+#pragma unroll
+            for (int r = 0; r < 12; ++r) {
+                saved_row_chunks<P, T>(W, g.Vs, ks, r, s, w);
+#pragma unroll
+                for (int q = 0; q < 12; ++q) cfma(acc[r], w[q], v[q]);
+            }
+        }
+#pragma unroll 1
+        for (int ks = 1; ks < kSaved; ++ks) {   // backward offsets: Gamma(W_{+d}(x - d)) psi(x - d)
+            const int k = saved_k(ks);
+            const int n = neighbour(g, x, y, z, t, -off_d(k, 0), -off_d(k, 1), -off_d(k, 2), -off_d(k, 3));
+            ld_spinor(psi, n, v);
+#pragma unroll
+            for (int p = 0; p < 12; ++p) {
+                saved_row_chunks<P, T>(W, g.Vs, ks, p, n, w);
+                const cpx<T> vv = v[(p + 6) % 12];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    const bool plus = (p < 6) == (q < 6);
+                    const cpx<T> c = plus ? conj(w[q]) : -conj(w[q]);
+                    cfma(acc[(q + 6) % 12], c, vv);
+                }
+            }
+        }
+        if constexpr (sizeof(T) == 8) {
+            double2* o = reinterpret_cast<double2*>(out) + (size_t)s * 12;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) o[q] = make_double2(acc[q].re, acc[q].im);
+        } else {
+            float4* o = reinterpret_cast<float4*>(out) + (size_t)s * 6;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                o[q] = make_float4(acc[2 * q].re, acc[2 * q].im, acc[2 * q + 1].re, acc[2 * q + 1].im);
+        }
+        if constexpr (EPI == EPI_RV) {
+            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(aux) + (size_t)s * 12;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const cpx<T> av = a[q];
+                d1.x += (double)av.re * acc[q].re + (double)av.im * acc[q].im;
+                d1.y += (double)av.re * acc[q].im - (double)av.im * acc[q].re;
+            }
+        } else if constexpr (EPI == EPI_TS) {
+            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const cpx<T> sv = a[q];
+                d1.x += (double)acc[q].re * sv.re + (double)acc[q].im * sv.im;
+                d1.y += (double)acc[q].re * sv.im - (double)acc[q].im * sv.re;
+                d2.x += (double)acc[q].re * acc[q].re + (double)acc[q].im * acc[q].im;
+            }
+        }
+    }
+    if constexpr (EPI != EPI_NONE) block_reduce2_store(d1, d2, partial);
+}
+
+template <int P>
+int launch_saved_t(const Geo& g, const void* W, const void* psi, void* out, double mhat, int epi, const void* aux,
+                   double2* partial, hipStream_t st) {
+    using T = typename Arith<P>::T;
+    const unsigned nb = grid_for(g.V, 256);
+    const T* in = reinterpret_cast<const T*>(psi);
+    T* o = reinterpret_cast<T*>(out);
+    const T* ax = reinterpret_cast<const T*>(aux);
+    if (epi == EPI_NONE) k_apply_saved<P, EPI_NONE><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
+    else if (epi == EPI_RV) k_apply_saved<P, EPI_RV><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
+    else k_apply_saved<P, EPI_TS><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
+    OK_LAUNCH_CHECK("k_apply_saved");
+    return OK_SUCCESS;
+}
+
 // FP64 W (plane layout) applied to NR right-hand sides in one pass, out_r = mhat in_r + sum_k W_k in_r(x+d_k):
 // each W element is loaded once and multiplied into every right-hand side.  TPS threads per site
 // (12/TPS output rows each); the right-hand sides are separate FP64 fields [V][12] named in `cols`.
@@ -255,8 +381,16 @@ int apply_blocks(const Geo& g, int tps) {
     return (int)grid_for((long)g.V * tps, 256);
 }
 
+// Wprec may carry OK_LAYOUT_SAVED (one thread per site; tps must then be 1)
 int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int tps,
                  int epi, const void* aux, double2* partial, hipStream_t st) {
+    if (Wprec & OK_LAYOUT_SAVED) {
+        switch (Wprec & 3) {
+            case OK_F64: return launch_saved_t<OK_F64>(g, W, psi, out, mhat, epi, aux, partial, st);
+            case OK_F32: return launch_saved_t<OK_F32>(g, W, psi, out, mhat, epi, aux, partial, st);
+            default: return launch_saved_t<OK_BF16>(g, W, psi, out, mhat, epi, aux, partial, st);
+        }
+    }
 #define OK_TPS_CASES(P)                                                                  \
     switch (tps) {                                                                       \
         case 1: return launch_apply_t<P, 1>(g, W, psi, out, mhat, epi, aux, partial, st); \

@@ -18,6 +18,12 @@
 // that layout FP32 blocks are stored column-major (entry 12*col + row), the
 // order in which the lanes of the FP32 MFMA read their A operands, and BF16
 // blocks row-major (the BF16 MFMA reads 4 consecutive columns per lane).
+//
+// With OK_LAYOUT_SAVED only the 14 blocks of the forward offsets (k = 0, +mu,
+// +2i, +i+j, +i-j: the saved set of Eq. FinalForm) are stored, plane-major as
+// above with the saved index ks in place of k; a backward block is formed
+// where it is used from the forward block of the neighbour it points to,
+// W_{-d,x} = gamma5 W_{+d,x-d}^dag gamma5 (Eq. conjugate).
 #pragma once
 
 #include "common.h"
@@ -41,13 +47,33 @@ template <> struct WL<OK_BF16> {
     static constexpr int esize = 4;
 };
 
-__host__ __device__ __forceinline__ size_t w_cell(int layout, int Vs, int ch, int k, int j, int s) {
-    return layout ? ((size_t)s * kW + k) * ch + j : ((size_t)(k * ch + j)) * Vs + s;
+// layout codes of the kernels: plane (27 blocks), site-major, saved set (14 blocks, plane)
+constexpr int LAY_PLANE = 0, LAY_SITE = 1, LAY_SAVED = 2;
+constexpr int kSaved = 14;
+// forward offset of saved index ks, and saved index of offset k (-1 for a backward offset)
+__host__ __device__ constexpr int saved_k(int ks) {
+    return ks <= 4 ? ks : ks <= 7 ? ks + 4 : ks <= 10 ? ks + 7 : ks + 10;
+}
+__host__ __device__ constexpr int saved_index(int k) {
+    return k <= 4 ? k : k <= 8 ? -1 : k <= 11 ? k - 4 : k <= 14 ? -1 : k <= 17 ? k - 7 : k <= 20 ? -1
+         : k <= 23 ? k - 10 : -1;
+}
+static_assert(saved_k(13) == 23 && saved_index(23) == 13 && saved_index(9) == 5 && saved_index(15) == 8 &&
+              saved_index(26) == -1 && saved_k(5) == 9, "saved set");
+
+inline int layout_of(int prec) {
+    return (prec & OK_LAYOUT_SITE) ? LAY_SITE : (prec & OK_LAYOUT_SAVED) ? LAY_SAVED : LAY_PLANE;
 }
 
-inline size_t w_bytes(int prec, int Vs) {
+__host__ __device__ __forceinline__ size_t w_cell(int layout, int Vs, int ch, int k, int j, int s) {
+    if (layout == LAY_SITE) return ((size_t)s * kW + k) * ch + j;
+    if (layout == LAY_SAVED) k = saved_index(k);
+    return ((size_t)(k * ch + j)) * Vs + s;
+}
+
+inline size_t w_bytes(int prec, int Vs, int layout = LAY_PLANE) {
     size_t es = prec == OK_F64 ? 16 : prec == OK_F32 ? 8 : 4;
-    return (size_t)kW * kWE * es * (size_t)Vs;
+    return (size_t)(layout == LAY_SAVED ? kSaved : kW) * kWE * es * (size_t)Vs;
 }
 
 // Store one row (12 complex, FP64 values) of block k at site s.
@@ -56,7 +82,7 @@ __device__ __forceinline__ void w_store_row(void* W, int Vs, int layout, int k, 
     uint4* base = reinterpret_cast<uint4*>(W);
     constexpr int per = WL<P>::per, ch = WL<P>::chunks;
     if constexpr (P == OK_F32) {
-        if (layout) {   // column-major block: entry (row, col) at 12*col + row
+        if (layout == LAY_SITE) {   // column-major block: entry (row, col) at 12*col + row
             float2* b = reinterpret_cast<float2*>(base + w_cell(layout, Vs, ch, k, 0, s));
 #pragma unroll
             for (int c = 0; c < 12; ++c) b[12 * c + row] = make_float2((float)v[c].re, (float)v[c].im);
@@ -91,7 +117,7 @@ __device__ __forceinline__ void w_store_row(void* W, int Vs, int layout, int k, 
 template <int P>
 __device__ __forceinline__ c128 w_load_entry(const void* W, int Vs, int layout, int k, int e, int s) {
     constexpr int per = WL<P>::per, ch = WL<P>::chunks;
-    if (P == OK_F32 && layout) e = 12 * (e % 12) + e / 12;   // column-major block
+    if (P == OK_F32 && layout == LAY_SITE) e = 12 * (e % 12) + e / 12;   // column-major block
     size_t cell = w_cell(layout, Vs, ch, k, e / per, s);
     if constexpr (P == OK_F64) {
         double2 d = reinterpret_cast<const double2*>(W)[cell];

@@ -22,6 +22,7 @@ _lib = C.CDLL(LIB_PATH)
 
 OK_F64, OK_F32, OK_BF16 = 0, 1, 2
 OK_LAYOUT_SITE = 0x10
+OK_LAYOUT_SAVED = 0x100
 OK_SPINOR_RHS_INNER = 0x20
 OK_NET_ADJOINT = 0x40
 OK_NET_MAX_LAYERS = 16

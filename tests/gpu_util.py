@@ -48,12 +48,12 @@ class Lattice:
         return ok.to_host_complex(d, I.lattice_shape(self.dims) + (27, 12, 12))
 
     def spinor_dtype(self, prec):
-        return "float64" if prec == self.ok.OK_F64 else "float32"
+        return "float64" if (prec & 3) == self.ok.OK_F64 else "float32"
 
     def apply_dev(self, prec, psi_dev, nrhs=1, c=None):
         ok = self.ok
         out = self.torch.empty_like(psi_dev)
-        sp = ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32
+        sp = ok.OK_F64 if (prec & 3) == ok.OK_F64 else ok.OK_F32
         ok.ok_apply_M(self.dims, c or self.c, self.precompute(prec), prec, psi_dev, out, sp, nrhs)
         return out
 
@@ -65,7 +65,7 @@ class Lattice:
         host = np.moveaxis(psi, 0, -1) if rhs_inner else psi
         d = ok.to_device_complex(np.ascontiguousarray(host), dtype=self.spinor_dtype(prec))
         out = self.torch.empty_like(d)
-        sp = ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32
+        sp = ok.OK_F64 if (prec & 3) == ok.OK_F64 else ok.OK_F32
         if rhs_inner:
             sp |= ok.OK_SPINOR_RHS_INNER
         ok.ok_apply_M(self.dims, c or self.c, self.precompute(prec), prec, d, out, sp, nrhs)

@@ -40,6 +40,17 @@ def test_abi_version():
     assert okinv.ok_abi_version() == 2
 
 
+def test_saved_layout_size_and_flags():
+    from paper_1311_5029_amd import okinv
+    dims = (5, 6, 7, 3)
+    for prec in (okinv.OK_F64, okinv.OK_F32, okinv.OK_BF16):
+        full = okinv.ok_W_bytes(dims, prec)
+        assert okinv.ok_W_bytes(dims, prec | okinv.OK_LAYOUT_SAVED) * 27 == full * 14
+    with pytest.raises(okinv.OkError) as e:
+        okinv.ok_W_bytes(dims, okinv.OK_F32 | okinv.OK_LAYOUT_SAVED | okinv.OK_LAYOUT_SITE)
+    assert e.value.status == okinv.OK_EINVAL
+
+
 def test_size_queries():
     from paper_1311_5029_amd import okinv
     dims = (20, 20, 20, 64)

@@ -179,6 +179,39 @@ def test_apply_deterministic(lat):
         assert np.array_equal(lat.apply(prec, psi), lat.apply(prec, psi))
 
 
+SAVED = 0x100   # OK_LAYOUT_SAVED
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "bf16"])
+def test_saved_layout_holds_same_numbers(lat, prec):
+    """The 14-block layout expands to exactly the 27 blocks of the full layout (the backward
+    ones are gamma5 conjugates of stored values, formed without rounding)."""
+    assert np.array_equal(lat.dense_W(prec | SAVED), lat.dense_W(prec))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "bf16"])
+def test_apply_saved_layout_matches_oracle(lat, prec):
+    psi = I.gaussian_sources(lat.dims, 2, 26)
+    ref = lat.oracle_B.apply(psi)
+    got = lat.apply(prec | SAVED, psi)
+    tol = TOL_APPLY[prec]
+    assert rel(got, ref) <= tol
+    assert maxrel(got, ref) <= tol * (1.0 if prec == 0 else 3.0)
+    # the same operator as the 27-block layout up to summation order
+    assert rel(got, lat.apply(prec, psi)) <= (1e-14 if prec == 0 else 1e-6 if prec == 1 else 1e-5)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 3, 5), (4, 4, 3, 4)], ids=["3x4x3x5", "4x4x3x4"])
+def test_apply_saved_small_lattices(dims):
+    """L = 3 and 4: the forward block read for a backward offset may be the site's own or a
+    coinciding neighbour's; the contributions still add up to M."""
+    ok = lib()
+    U, c = make(dims, seed=6)
+    L = Lattice(dims, U, c)
+    psi = I.gaussian_sources(dims, 1, 27)[0]
+    assert rel(L.apply(ok.OK_F64 | SAVED, psi), OKOperatorB(U, c).apply(psi)) < 1e-12
+
+
 def test_apply_l3_coinciding_offsets():
     """L = 3: x + 2i coincides with x - i, the contributions add."""
     ok = lib()
@@ -218,7 +251,8 @@ def big():
     return L
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 0x100, 0x101, 0x102],
+                         ids=["f64", "f32", "bf16", "f64-saved", "f32-saved", "bf16-saved"])
 def test_full_size_sampled_sites(big, prec):
     """Sampled sites of M psi at 20^3 x 64 against the oracle evaluated site by site."""
     psi = I.gaussian_sources(big.dims, 1, 31)[0]
@@ -228,7 +262,7 @@ def test_full_size_sampled_sites(big, prec):
                                                 for _ in range(6)]
     ref = apply_at_sites(big.U, psi, big.c, sites)
     gs = np.stack([got[t, z, y, x] for (x, y, z, t) in sites])
-    assert rel(gs, ref) <= TOL_APPLY[prec]
+    assert rel(gs, ref) <= TOL_APPLY[prec & 3]
 
 
 @pytest.mark.parametrize("prec,inner", [(1, False), (2, False), (1 | SITE, False), (2 | SITE, False),
