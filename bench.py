@@ -134,7 +134,9 @@ def parse_pmc(fetch_dir, write_dir, form):
         for cname in ("FETCH_SIZE", "WRITE_SIZE"):
             ker = [v[cname] for (k, _), v in rows[cname].items() if cname in v and is_apply_kernel(k, form, kernel)]
             cop = [v[cname] for (k, _), v in rows[cname].items() if "copy" in k.lower() and cname in v]
-            cop = [x for x in cop if x * 1024 > 0.5 * COPY_BYTES]
+            # the 1 GiB calibration copy (the counters read 0.5 and 1 GiB for it), not the 4 GiB
+            # bandwidth copy the benchmark also runs
+            cop = [x for x in cop if 0.25 * COPY_BYTES < x * 1024 < 1.5 * COPY_BYTES]
             if not ker or not cop:
                 break
             scale = COPY_BYTES / (1024.0 * float(np.median(cop)))
