@@ -444,7 +444,9 @@ def net_kernels(args):
             out["kernels"][key] = {"ms": round(ms, 4), "GB/s": round(by / ms / 1e6, 1),
                                    "TFLOP/s": round(fl_ / ms / 1e9, 2),
                                    "frac_hbm": round(by / ms / 1e6 / HBM_PEAK_GBS, 4),
-                                   "frac_fp32_valu": round(fl_ / ms / 1e9 / 157.3, 4)}
+                                   "frac_fp32_valu": round(fl_ / ms / 1e9 / 157.3, 4),
+                                   # without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+                                   "frac_fp32_valu_unpacked": round(fl_ / ms / 1e9 / 78.6, 4)}
             log("%s %s" % (key, out["kernels"][key]))
         del x, y, work
     print(json.dumps(out), flush=True)
