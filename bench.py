@@ -38,6 +38,8 @@ NRHS = 12
 BYTES_SITE = {0: 27 * 144 * 16 + 2 * 192, 1: 27 * 144 * 8 + 2 * 96, 2: 27 * 144 * 4 + 2 * 96}
 # the 14-block saved set (OK_LAYOUT_SAVED): each stored block read once from HBM
 BYTES_SAVED = {0: 14 * 144 * 16 + 2 * 192, 1: 14 * 144 * 8 + 2 * 96, 2: 14 * 144 * 4 + 2 * 96}
+# W as 46 Pauli-component colour matrices per site (OK_LAYOUT_SIGMA), each read once from HBM
+BYTES_SIGMA = {0: 46 * 9 * 16 + 2 * 192, 1: 46 * 9 * 8 + 2 * 96}
 # ... and of one application to the 12-RHS batch by the MFMA kernel: W streamed
 # once for all right-hand sides + 12 spinors in and out (FP64 W: 12 single launches)
 BYTES_STEP = {0: NRHS * BYTES_SITE[0], 1: 27 * 144 * 8 + NRHS * 2 * 96, 2: 27 * 144 * 4 + NRHS * 2 * 96}
@@ -512,9 +514,9 @@ def main():
     SITE, INNER = ok.OK_LAYOUT_SITE, ok.OK_SPINOR_RHS_INNER
     Ws = {}
     pre_ms = {}
-    SAVED = ok.OK_LAYOUT_SAVED
+    SAVED, SIGMA = ok.OK_LAYOUT_SAVED, ok.OK_LAYOUT_SIGMA
     wforms = [ok.OK_F64, ok.OK_F32, ok.OK_BF16, ok.OK_F32 | SITE, ok.OK_BF16 | SITE,
-              ok.OK_F64 | SAVED, ok.OK_F32 | SAVED, ok.OK_BF16 | SAVED]
+              ok.OK_F64 | SAVED, ok.OK_F32 | SAVED, ok.OK_BF16 | SAVED, ok.OK_F64 | SIGMA, ok.OK_F32 | SIGMA]
     for prec in wforms:
         Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(DIMS, prec))
         scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(DIMS))
@@ -523,7 +525,8 @@ def main():
         ok.ok_precompute_W(DIMS, c, links, prec, Ws[prec], scr)
         e1.record()
         torch.cuda.synchronize()
-        pre_ms[PREC_NAME[prec & 3] + ("_site" if prec & SITE else "_saved" if prec & SAVED else "")] = \
+        pre_ms[PREC_NAME[prec & 3] + ("_site" if prec & SITE else "_saved" if prec & SAVED else
+                                      "_sigma" if prec & SIGMA else "")] = \
             round(e0.elapsed_time(e1), 3)
         del scr
     log("precompute ms %s" % pre_ms)
@@ -575,13 +578,15 @@ def main():
     # context: one right-hand side (plane W), and the batched forms
     apply_forms = {}
     for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
-        for lay in (0, SAVED):
+        for lay in (0, SAVED, SIGMA):
+            if lay == SIGMA and prec == ok.OK_BF16:
+                continue
             ms = time_apply(prec | lay, ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32, 1)
-            # the saved layout streams 14 of the 27 blocks per site (the other 13 are reread from
-            # neighbours); its GB/s counts the bytes of the layout it reads once
-            by = BYTES_SAVED[prec] if lay else BYTES_SITE[prec]
+            # the saved and sigma layouts stream their stored set once per site (the backward
+            # blocks are reread from neighbours); their GB/s counts the bytes of that set
+            by = BYTES_SAVED[prec] if lay == SAVED else BYTES_SIGMA[prec] if lay == SIGMA else BYTES_SITE[prec]
             gbs = by * V / (ms * 1e-3) / 1e9
-            apply_forms["1rhs_" + PREC_NAME[prec] + ("_saved" if lay else "")] = {
+            apply_forms["1rhs_" + PREC_NAME[prec] + ("_saved" if lay == SAVED else "_sigma" if lay else "")] = {
                 "ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "rhs_sites_per_s": round(V / (ms * 1e-3), 0)}
     for prec in (ok.OK_F32, ok.OK_BF16):
@@ -610,25 +615,38 @@ def main():
     log("4 GiB device copy: %.1f GB/s" % copy_gbs)
 
     # ---- time to solution: plain vs chosen, the 12 point sources --------------------
+    # plain: FP64 W (27 dense blocks), FP64 fields, one source after the other.  The other forms
+    # change only the storage of W and the arithmetic of the inner solve; every one stops on
+    # the FP64 true residual.  chosen = the fastest of them (median of three solves each).
     solve = None
     if not args.no_solve:
         xi = ok.to_device_complex(cfg["xi"])
         res = {}
-        for name, low, reps in (("plain", None, 1), ("chosen", ok.OK_BF16 | SITE, 3)):
+        forms = (("plain", None, 0, 1, "FP64 W (27 dense blocks), FP64 fields, one RHS after the other"),
+                 ("plain_sigma", None, SIGMA, 1, "FP64 W as 46 Pauli-component colour matrices per site, FP64 "
+                                                 "fields, one RHS after the other"),
+                 ("batched_bf16", ok.OK_BF16 | SITE, 0, 3, "12 RHS together: BF16 W on the matrix cores, FP32 "
+                                                           "fields, FP64 reliable updates (dense FP64 W)"),
+                 ("batched_bf16_sigma64", ok.OK_BF16 | SITE, SIGMA, 3, "as batched_bf16, FP64 reliable updates "
+                                                                       "with the sigma-layout FP64 W"),
+                 ("mixed_f32_sigma", ok.OK_F32 | SIGMA, SIGMA, 3, "one RHS after the other: FP32 sigma-layout W, "
+                                                                  "FP32 fields, FP64 reliable updates (sigma W)"))
+        for name, low, w64, reps, desc in forms:
             lp = -1 if low is None else low
             work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(DIMS, NRHS, lp))
+            params = ok.SolverParams(tol=1e-10, W64_layout=w64)
             secs = []
-            for _ in range(reps):   # the chosen solve: median of three
+            for _ in range(reps):
                 psi = torch.zeros_like(xi)
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                rc, st = ok.ok_bicgstab(DIMS, c, ok.SolverParams(tol=1e-10), Ws[ok.OK_F64],
+                rc, st = ok.ok_bicgstab(DIMS, c, params, Ws[ok.OK_F64 | w64],
                                         None if low is None else Ws[low], lp, xi, psi, NRHS, work, stream)
                 torch.cuda.synchronize()
                 secs.append(time.perf_counter() - t)
             sec = float(np.median(secs))
             res[name] = {
-                "seconds": round(sec, 3), "status": rc, "repeats": reps,
+                "form": desc, "seconds": round(sec, 3), "status": rc, "repeats": reps,
                 "iterations": int(sum(s["iterations"] for s in st)),
                 "matvec_f64": int(sum(s["matvec_hi"] for s in st)),
                 "matvec_low": int(sum(s["matvec_lo"] for s in st)),
@@ -637,11 +655,11 @@ def main():
             }
             log("solve %s: %s" % (name, res[name]))
             del work, psi
+        best = min((k for k in res if k != "plain"), key=lambda k: res[k]["seconds"])
         solve = {"workload": "12 point sources to ||xi-M psi||/||xi|| <= 1e-10 (FP64 true residual)",
-                 "plain": dict(form="FP64 W, FP64 fields, one RHS after the other", **res["plain"]),
-                 "chosen": dict(form="12 RHS together: BF16 W on the matrix cores, FP32 fields, "
-                                     "FP64 reliable updates", **res["chosen"]),
-                 "speedup": round(res["plain"]["seconds"] / res["chosen"]["seconds"], 3)}
+                 "plain": res["plain"], "chosen": dict(name=best, **res[best]),
+                 "speedup": round(res["plain"]["seconds"] / res[best]["seconds"], 3),
+                 "forms": res}
 
     cpu = None
     if not args.no_cpu:

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define OKINV_ABI_VERSION 2
+#define OKINV_ABI_VERSION 3
 
 /* Status codes.  0 success, > 0 solver outcomes (stats filled), < 0 errors. */
 enum ok_status {
@@ -77,6 +77,17 @@ enum ok_prec { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2 };
  * with OK_LAYOUT_SITE). */
 #define OK_LAYOUT_SAVED 0x100
 
+/* Layout flag OR-ed into the W precision (OK_F64 or OK_F32) of ok_W_bytes,
+ * ok_precompute_W, ok_apply_M and ok_W_to_dense: every forward block is kept as
+ * the colour matrices of its Pauli decomposition in spin (Sec. 2.2: each 2x2
+ * spin block of Eqs. shifted_W_first..last is a sum of sigma_n (x) colour
+ * matrix), 46 per site, and the blocks are formed where they are used, the
+ * backward ones by Eq. conjugate.  3,312 bytes per site in FP32 and 6,624 in
+ * FP64 against 31,104 and 62,208 for 27 dense blocks, for the same operator
+ * (up to rounding: W0 and W+_i are stored as half sums and differences of
+ * their two spin blocks).  One right-hand side at a time. */
+#define OK_LAYOUT_SIGMA 0x200
+
 /* Spinor layout flag OR-ed into spinor_prec of ok_apply_M (FP32 spinors,
  * site-major W, nrhs <= 16): spinors stored [V][4][3][nrhs] complex, the
  * right-hand side index fastest, which the multi-right-hand-side kernel reads
@@ -106,6 +117,8 @@ typedef struct ok_solver_params {
                                new minimum for this many iterations is a stall
                                and hands over to the unpreconditioned solve;
                                0: off                                           */
+    int32_t W64_layout;     /* layout of d_W64: 0 (27 dense blocks, plane-major),
+                               OK_LAYOUT_SAVED or OK_LAYOUT_SIGMA               */
 } ok_solver_params;
 
 typedef struct ok_solver_stats {
@@ -175,10 +188,12 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const 
                                 size_t* bytes);
 
 /* Solve M psi = xi for nrhs right-hand sides by BiCGStab (Sec. 2.3).
- *   d_W64   FP64 W, plane layout (always needed: residuals and the final
- *           check are FP64).
+ *   d_W64   FP64 W in the layout params->W64_layout (always needed: residuals
+ *           and the final check are FP64).
  *   d_Wlo   NULL: plain FP64 BiCGStab.  Otherwise W at Wlo_prec (OK_F32 or
- *           OK_BF16): the iteration runs in FP32 fields with that operator and
+ *           OK_BF16, optionally | OK_LAYOUT_SAVED, or OK_F32 | OK_LAYOUT_SIGMA,
+ *           for one right-hand side at a time; or | OK_LAYOUT_SITE, below):
+ *           the iteration runs in FP32 fields with that operator and
  *           FP64 reliable updates (x accumulated and r recomputed in FP64 when
  *           the low-precision residual drops by params->delta).  With
  *           Wlo_prec | OK_LAYOUT_SITE the right-hand sides (in groups of up to

@@ -84,9 +84,11 @@ static bool valid_prec(int p) { return p == OK_F64 || p == OK_F32 || p == OK_BF1
 
 // W precision with an optional layout flag: OK_LAYOUT_SITE (FP32 and BF16) or OK_LAYOUT_SAVED
 static bool valid_wprec(int p) {
-    const int b = p & ~(OK_LAYOUT_SITE | OK_LAYOUT_SAVED);
-    if ((p & OK_LAYOUT_SITE) && (p & OK_LAYOUT_SAVED)) return false;
-    if (p & OK_LAYOUT_SITE) return b == OK_F32 || b == OK_BF16;
+    const int lay = p & (OK_LAYOUT_SITE | OK_LAYOUT_SAVED | OK_LAYOUT_SIGMA);
+    const int b = p & ~(OK_LAYOUT_SITE | OK_LAYOUT_SAVED | OK_LAYOUT_SIGMA);
+    if (lay & (lay - 1)) return false;   // at most one layout flag
+    if (lay == OK_LAYOUT_SITE) return b == OK_F32 || b == OK_BF16;
+    if (lay == OK_LAYOUT_SIGMA) return b == OK_F64 || b == OK_F32;
     return valid_prec(b);
 }
 
@@ -200,7 +202,7 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
     }
     const int wbase = W_prec & 3;
     const bool site_major = (W_prec & OK_LAYOUT_SITE) != 0;
-    const bool saved = (W_prec & OK_LAYOUT_SAVED) != 0;
+    const bool saved = (W_prec & (OK_LAYOUT_SAVED | OK_LAYOUT_SIGMA)) != 0;   // one thread per site
     const bool rhs_inner = (spinor_prec & OK_SPINOR_RHS_INNER) != 0;
     if (rhs_inner && (!site_major || nrhs > 16)) {
         set_error("OK_SPINOR_RHS_INNER needs site-major W (OK_LAYOUT_SITE) and nrhs <= 16");

@@ -266,6 +266,148 @@ struct PreCoef {
 constexpr int kPairI[3] = {0, 0, 1};
 constexpr int kPairJ[3] = {1, 2, 2};
 
+// ------------------------------------------------------------------ Pauli-decomposed storage
+// Row a (three FP64 entries) of colour matrix mi of site s, stored at precision P (LAY_SIGMA).
+template <int P>
+__device__ __forceinline__ void sigma_store_row(void* W, int Vs, int mi, int a, int s, const c128 r[3]) {
+    char* base = reinterpret_cast<char*>(W);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const size_t off = sigma_off<P>(Vs, mi, 3 * a + b, s);
+        if constexpr (P == OK_F64) *reinterpret_cast<double2*>(base + off) = make_double2(r[b].re, r[b].im);
+        else *reinterpret_cast<float2*>(base + off) = make_float2((float)r[b].re, (float)r[b].im);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void sigma_load_row(const void* W, int Vs, int mi, int a, int s, c128 r[3]) {
+    const char* base = reinterpret_cast<const char*>(W);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const size_t off = sigma_off<P>(Vs, mi, 3 * a + b, s);
+        if constexpr (P == OK_F64) {
+            const double2 d = *reinterpret_cast<const double2*>(base + off);
+            r[b] = c128{d.x, d.y};
+        } else {
+            const float2 f = *reinterpret_cast<const float2*>(base + off);
+            r[b] = c128{(double)f.x, (double)f.y};
+        }
+    }
+}
+
+// Forward block f (0: W0, 1..3: W+_i, 4: W+_4, 5..7: W++_ii, 8..10: W++_ij, 11..13: W+-_ij),
+// colour row a, from its two Pauli-decomposed spin blocks: store the matrices listed in wlayout.h.
+template <int P>
+__device__ void sigma_store_block(void* W, int Vs, int f, int a, int s, const Half& H1, const Half& H2) {
+    c128 r[3];
+    if (f == 0) {
+#pragma unroll
+        for (int m = 1; m <= 3; ++m) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)   // (X1 - i X2) / 2
+                r[b] = c128{0.5 * (H1.h[m][b].re + H2.h[m][b].im), 0.5 * (H1.h[m][b].im - H2.h[m][b].re)};
+            sigma_store_row<P>(W, Vs, SG_W0 + m - 1, a, s, r);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)   // (X1 + i X2) / 2
+                r[b] = c128{0.5 * (H1.h[m][b].re - H2.h[m][b].im), 0.5 * (H1.h[m][b].im + H2.h[m][b].re)};
+            sigma_store_row<P>(W, Vs, SG_W0 + 2 + m, a, s, r);
+        }
+    } else if (f <= 3) {
+        const int base = SG_WI + 8 * (f - 1);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) r[b] = 0.5 * (H1.h[n][b] + H2.h[n][b]);
+            sigma_store_row<P>(W, Vs, base + n, a, s, r);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) r[b] = 0.5 * (H1.h[n][b] - H2.h[n][b]);
+            sigma_store_row<P>(W, Vs, base + 4 + n, a, s, r);
+        }
+    } else if (f == 4) {
+#pragma unroll
+        for (int m = 1; m <= 3; ++m) sigma_store_row<P>(W, Vs, SG_W4 + m - 1, a, s, H1.h[m]);
+        sigma_store_row<P>(W, Vs, SG_W4 + 3, a, s, H2.h[0]);
+    } else if (f <= 7) {
+        const int i = f - 5;
+        sigma_store_row<P>(W, Vs, SG_WII + 2 * i, a, s, H1.h[0]);
+        sigma_store_row<P>(W, Vs, SG_WII + 2 * i + 1, a, s, H2.h[1 + i]);
+    } else if (f <= 10) {
+        sigma_store_row<P>(W, Vs, SG_WIJ + f - 8, a, s, H1.h[1 + kPairI[f - 8]]);
+    } else {
+        sigma_store_row<P>(W, Vs, SG_WIMJ + f - 11, a, s, H1.h[1 + kPairI[f - 11]]);
+    }
+}
+
+// Inverse of sigma_store_block: the two spin blocks (row a) and the shape of forward block f.
+template <int P>
+__device__ void sigma_load_block(const void* W, int Vs, int f, int a, int s, Half& H1, Half& H2, int& shape) {
+    hzero(H1);
+    hzero(H2);
+    c128 r[3], q[3];
+    if (f == 0) {
+        shape = SH_W0;
+#pragma unroll
+        for (int m = 1; m <= 3; ++m) {
+            sigma_load_row<P>(W, Vs, SG_W0 + m - 1, a, s, r);   // (X1 - i X2) / 2
+            sigma_load_row<P>(W, Vs, SG_W0 + 2 + m, a, s, q);   // (X1 + i X2) / 2
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                H1.h[m][b] = r[b] + q[b];
+                const c128 d = r[b] - q[b];                      // -i X2
+                H2.h[m][b] = c128{-d.im, d.re};                  // i (-i X2)
+            }
+        }
+    } else if (f <= 3) {
+        shape = SH_DS;
+        const int base = SG_WI + 8 * (f - 1);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            sigma_load_row<P>(W, Vs, base + n, a, s, r);
+            sigma_load_row<P>(W, Vs, base + 4 + n, a, s, q);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                H1.h[n][b] = r[b] + q[b];
+                H2.h[n][b] = r[b] - q[b];
+            }
+        }
+    } else if (f == 4) {
+        shape = SH_T4;
+#pragma unroll
+        for (int m = 1; m <= 3; ++m) sigma_load_row<P>(W, Vs, SG_W4 + m - 1, a, s, H1.h[m]);
+        sigma_load_row<P>(W, Vs, SG_W4 + 3, a, s, H2.h[0]);
+    } else if (f <= 7) {
+        shape = SH_DS;
+        const int i = f - 5;
+        sigma_load_row<P>(W, Vs, SG_WII + 2 * i, a, s, H1.h[0]);
+        sigma_load_row<P>(W, Vs, SG_WII + 2 * i + 1, a, s, H2.h[1 + i]);
+    } else {
+        shape = SH_OFF;
+        const bool plus = f <= 10;
+        const int p = plus ? f - 8 : f - 11;
+        sigma_load_row<P>(W, Vs, (plus ? SG_WIJ : SG_WIMJ) + p, a, s, r);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            H1.h[1 + kPairI[p]][b] = r[b];
+            H1.h[1 + kPairJ[p]][b] = plus ? r[b] : -r[b];
+        }
+    }
+}
+
+// Row (alpha, a) of a block from its spin blocks: entry (beta, b) = sum of the spin blocks at (alpha/2, beta/2).
+__device__ __forceinline__ void expand_row(int shape, int al, const Half& H1, const Half& H2, c128 v[12]) {
+#pragma unroll
+    for (int be = 0; be < 4; ++be) {
+        double w1, w2;
+        shape_weights(shape, al >> 1, be >> 1, w1, w2);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            c128 e1 = half_entry(H1, al & 1, be & 1, b);
+            c128 e2 = half_entry(H2, al & 1, be & 1, b);
+            v[3 * be + b] = w1 * e1 + w2 * e2;
+        }
+    }
+}
+
 template <int P>
 __global__ void __launch_bounds__(64) k_forward(Geo g, PreCoef q, const double* links, const double2* F,
                                                 void* W, int layout) {
@@ -404,21 +546,15 @@ __global__ void __launch_bounds__(64) k_forward(Geo g, PreCoef q, const double* 
         hacc(H1, 1 + j, c128{-q.cOff, 0.0}, t1);
     }
 
+    if (layout == LAY_SIGMA) {
+        if constexpr (P != OK_BF16) sigma_store_block<P>(W, Vs, f, a, s, H1, H2);
+        return;
+    }
     // expand: row (alpha, a) of W, entry (beta, b) = sum of the spin blocks at (alpha/2, beta/2)
 #pragma unroll
     for (int al = 0; al < 4; ++al) {
         c128 v[12];
-#pragma unroll
-        for (int be = 0; be < 4; ++be) {
-            double w1, w2;
-            shape_weights(shape, al >> 1, be >> 1, w1, w2);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                c128 e1 = half_entry(H1, al & 1, be & 1, b);
-                c128 e2 = half_entry(H2, al & 1, be & 1, b);
-                v[3 * be + b] = w1 * e1 + w2 * e2;
-            }
-        }
+        expand_row(shape, al, H1, H2, v);
         w_store_row<P>(W, Vs, layout, k, 3 * al + a, s, v);
     }
 }
@@ -458,6 +594,41 @@ __global__ void __launch_bounds__(64) k_to_dense(Geo g, const void* W, int layou
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     const int k = blockIdx.y, row = blockIdx.z;
+    if constexpr (P != OK_BF16) {
+        if (layout == LAY_SIGMA) {
+            // forward block f of offset kf, expanded from its matrices; a backward offset takes
+            // gamma5 (forward block at x - d)^dag gamma5 entry by entry
+            const int ks = saved_index(k);
+            int kf = k;
+            if (ks < 0)
+                for (int i = 0; i < 13; ++i)
+                    if (kBwd[i] == k) kf = kFwdOf[i];
+            const int f = kf == 0 ? 0 : kf <= 3 ? kf : kf == 4 ? 4 : kf <= 11 ? kf - 4 : kf <= 17 ? kf - 7 : kf - 10;
+            int x, y, z, t;
+            site_coords(g, s, x, y, z, t);
+            const int src = ks >= 0 ? s : neighbour(g, x, y, z, t, -off_d(kf, 0), -off_d(kf, 1), -off_d(kf, 2), -off_d(kf, 3));
+            const int al = row / 3, a = row % 3;
+            Half H1, H2;
+            int shape;
+            c128 v[12];
+            if (ks >= 0) {
+                sigma_load_block<P>(W, g.Vs, f, a, src, H1, H2, shape);
+                expand_row(shape, al, H1, H2, v);
+                for (int col = 0; col < 12; ++col) dense[((size_t)s * kW + k) * kWE + row * 12 + col] = make_double2(v[col].re, v[col].im);
+                return;
+            }
+            for (int be = 0; be < 4; ++be)
+                for (int b = 0; b < 3; ++b) {
+                    // Gamma(X)[(al,a),(be,b)] = sg * conj(X[(be^2, b), (al^2, a)])
+                    sigma_load_block<P>(W, g.Vs, f, b, src, H1, H2, shape);
+                    expand_row(shape, be ^ 2, H1, H2, v);
+                    const c128 xv = v[3 * (al ^ 2) + a];
+                    const double sg = ((al < 2) == (be < 2)) ? 1.0 : -1.0;
+                    dense[((size_t)s * kW + k) * kWE + row * 12 + 3 * be + b] = make_double2(sg * xv.re, -sg * xv.im);
+                }
+            return;
+        }
+    }
     if (layout == LAY_SAVED && saved_index(k) < 0) {
         // backward block of the saved set: gamma5 (forward block at x - d)^dag gamma5
         int kf = 0;
@@ -491,7 +662,7 @@ int run_precompute(const Geo& g, const PreCoef& q, const double* links, void* W,
     OK_LAUNCH_CHECK("k_clover");
     k_forward<P><<<dim3(nb, 14, 3), 64, 0, st>>>(g, q, links, F, W, layout);
     OK_LAUNCH_CHECK("k_forward");
-    if (layout != LAY_SAVED) {   // the saved set forms its backward blocks where they are used
+    if (layout != LAY_SAVED && layout != LAY_SIGMA) {   // these form their backward blocks where they are used
         k_backward<P><<<dim3(nb, 13, 12), 64, 0, st>>>(g, W, layout);
         OK_LAUNCH_CHECK("k_backward");
     }

@@ -95,6 +95,7 @@ struct Ctx {
     const ok_net* net;   // the preconditioner of the current solve, or NULL
     hipStream_t st;
     Work w;
+    int W64_prec;        // OK_F64 | the layout of W64
     int tps64, tpslo;
 };
 
@@ -115,7 +116,7 @@ int fin_blas(Ctx& C, int kind) { return fin(C, kind, blas_blocks(C.g)); }
 // t = M64 x ; r64 = xi - t ; rlo = (float) r64 (if given) ; returns ||r64||^2 on the host
 int true_residual(Ctx& C, const double* xi, const double* x, double* t, double* r64, float* rlo, double* rr,
                   ok_solver_stats* S) {
-    OK_TRY(launch_apply(C.g, C.W64, OK_F64, x, t, C.c->mhat, C.tps64, EPI_NONE, nullptr, nullptr, C.st));
+    OK_TRY(launch_apply(C.g, C.W64, C.W64_prec, x, t, C.c->mhat, C.tps64, EPI_NONE, nullptr, nullptr, C.st));
     S->matvec_hi++;
     OK_TRY(launch_residual(C.g, xi, t, r64, rlo, C.w.partial, C.st));
     OK_TRY(fin_blas(C, FIN_TRUE));
@@ -202,7 +203,7 @@ int solve_plain(Ctx& C, const double* xi, double* x, ok_solver_stats* S) {
             S->true_rel_resid = std::sqrt(rr) / xn;
             return S->status = (S->true_rel_resid <= P.tol) ? OK_SUCCESS : OK_NOT_CONVERGED;
         }
-        OK_TRY(iterate(C, true, C.W64, OK_F64, C.tps64, x, r, rhat, p, v, s, t));
+        OK_TRY(iterate(C, true, C.W64, C.W64_prec, C.tps64, x, r, rhat, p, v, s, t));
         S->matvec_hi += 2;
         S->iterations++;
         OK_TRY(read_scal(C, &h));
@@ -388,7 +389,13 @@ int batched_true_residuals(Ctx& C, WorkB& B, int nrhs, const int* cols, int n, c
             in[r] = x + cols[i0 + r] * col;
             out[r] = B.t64 + (size_t)r * col;
         }
-        OK_TRY(launch_apply_m64(g, C.W64, in, out, m, C.c->mhat, C.st));
+        if (C.W64_prec == OK_F64) {
+            OK_TRY(launch_apply_m64(g, C.W64, in, out, m, C.c->mhat, C.st));
+        } else {   // saved or sigma layout: one single-right-hand-side application per column
+            for (int r = 0; r < m; ++r)
+                OK_TRY(launch_apply(g, C.W64, C.W64_prec, in[r], out[r], C.c->mhat, 1, EPI_NONE, nullptr, nullptr,
+                                    C.st));
+        }
         for (int r = 0; r < m; ++r) {
             const int j = cols[i0 + r];
             S[j].matvec_hi++;
@@ -598,6 +605,14 @@ extern "C" {
 
 namespace {
 
+// low-precision operator of a mixed solve: F32 / BF16, at most one layout flag, sigma only in F32
+bool valid_wlo(int p) {
+    const int lay = p & (OK_LAYOUT_SITE | OK_LAYOUT_SAVED | OK_LAYOUT_SIGMA), b = p & ~lay;
+    if (lay & (lay - 1)) return false;
+    if (lay == OK_LAYOUT_SIGMA) return b == OK_F32;
+    return b == OK_F32 || b == OK_BF16;
+}
+
 int check_solver_net(const ok_net* net, bool mixed) {
     if (!net) return OK_SUCCESS;
     if (!mixed) {
@@ -628,9 +643,9 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const 
         set_error("nrhs must be >= 1 and bytes non-NULL");
         return OK_EINVAL;
     }
-    const int wb = Wlo_prec & ~OK_LAYOUT_SITE;
-    if (Wlo_prec >= 0 && wb != OK_F32 && wb != OK_BF16) {
-        set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE), or negative (plain FP64)");
+    if (Wlo_prec >= 0 && !valid_wlo(Wlo_prec)) {
+        set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE or OK_LAYOUT_SAVED), "
+                  "OK_F32 | OK_LAYOUT_SIGMA, or negative (plain FP64)");
         return OK_EINVAL;
     }
     if ((rc = check_solver_net(net, Wlo_prec >= 0))) return rc;
@@ -662,9 +677,14 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
         return OK_EINVAL;
     }
     const bool mixed = d_Wlo != nullptr;
-    const int wlb = Wlo_prec & ~OK_LAYOUT_SITE;
-    if (mixed && wlb != OK_F32 && wlb != OK_BF16) {
-        set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE) when d_Wlo is given");
+    const int wlb = Wlo_prec & 3;
+    if (mixed && !valid_wlo(Wlo_prec)) {
+        set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE or OK_LAYOUT_SAVED), or "
+                  "OK_F32 | OK_LAYOUT_SIGMA, when d_Wlo is given");
+        return OK_EINVAL;
+    }
+    if (p->W64_layout != 0 && p->W64_layout != OK_LAYOUT_SAVED && p->W64_layout != OK_LAYOUT_SIGMA) {
+        set_error("params->W64_layout must be 0, OK_LAYOUT_SAVED or OK_LAYOUT_SIGMA");
         return OK_EINVAL;
     }
     if ((rc = check_solver_net(net, mixed))) return rc;
@@ -698,8 +718,9 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
     C.Wlo_prec = Wlo_prec;
     C.net = net;
     C.st = reinterpret_cast<hipStream_t>(stream);
-    C.tps64 = stencil_tps(OK_F64);
-    C.tpslo = mixed ? stencil_tps(wlb) : 1;
+    C.W64_prec = OK_F64 | p->W64_layout;
+    C.tps64 = p->W64_layout ? 1 : stencil_tps(OK_F64);
+    C.tpslo = !mixed || (Wlo_prec & (OK_LAYOUT_SAVED | OK_LAYOUT_SIGMA)) ? 1 : stencil_tps(wlb);
     // the fallback continues from the iterate in d_psi
     ok_solver_params pf = *p;
     pf.zero_guess = 0;

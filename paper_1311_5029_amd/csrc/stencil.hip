@@ -381,9 +381,10 @@ int apply_blocks(const Geo& g, int tps) {
     return (int)grid_for((long)g.V * tps, 256);
 }
 
-// Wprec may carry OK_LAYOUT_SAVED (one thread per site; tps must then be 1)
+// Wprec may carry OK_LAYOUT_SAVED or OK_LAYOUT_SIGMA (one thread per site; tps must then be 1)
 int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int tps,
                  int epi, const void* aux, double2* partial, hipStream_t st) {
+    if (Wprec & OK_LAYOUT_SIGMA) return launch_apply_sigma(g, W, Wprec, psi, out, mhat, epi, aux, partial, st);
     if (Wprec & OK_LAYOUT_SAVED) {
         switch (Wprec & 3) {
             case OK_F64: return launch_saved_t<OK_F64>(g, W, psi, out, mhat, epi, aux, partial, st);

@@ -1,0 +1,364 @@
+// The 27-point operator (Eq. minFlopForm) with W kept as the colour matrices of its Pauli
+// decomposition in spin (OK_LAYOUT_SIGMA, 46 matrices per site; wlayout.h lists them).
+//
+// Every spin block of Eqs. shifted_W_first..last is a sum over sigma_n (x) colour matrix, and
+// the forward blocks come in four shapes:
+//   [[A, B], [B, A]]   (W+_i, W++_ii):  out_u +- out_d = (A +- B)(psi_u +- psi_d)
+//   [[A, B], [-B, A]]  (W0):            out_u +- i out_d = (A -+ i B)(psi_u +- i psi_d)
+//   [[0, H], [H, N]]   (W+_4)
+//   [[0, H], [H, 0]]   (W++_ij, W+-_ij, H = (sigma_i +- sigma_j) (x) T)
+// (u, d: the upper and lower spin pairs).  A backward block W_{-d,x} = gamma5 W_{+d,x-d}^dag
+// gamma5 (Eq. conjugate) is [[D^dag, -B^dag], [-C^dag, A^dag]] of the forward block
+// [[A, B], [C, D]] at x - d; since the sigma_n are hermitian that only takes colour
+// daggers: the [[A, B], [B, A]] shape maps to itself with (A + B, A - B) -> ((A - B)^dag,
+// (A + B)^dag), the off-diagonal one to -H^dag, and [[0, H], [H, N]] to [[N^dag, -H^dag],
+// [-H^dag, 0]].
+//
+// One thread per site.  Per site and application: 46 matrices (3,312 B FP32, 6,624 B FP64)
+// read at the site and again as the backward blocks of its neighbours, one spinor out, and
+// 27 neighbour spinors (L2 hits mostly); 232 colour matrix-vector products (2,088 complex
+// multiply-adds, against 3,888 for 27 dense blocks).
+#include "common.h"
+#include "kernels.h"
+#include "wlayout.h"
+
+namespace okinv {
+namespace {
+
+template <int P> struct SArith { using T = float; };
+template <> struct SArith<OK_F64> { using T = double; };
+
+// colour matrix mi of site s (row-major 3x3)
+template <int P, typename T>
+__device__ __forceinline__ void ld_mat(const void* __restrict__ W, int Vs, int mi, int s, cpx<T> M[9]) {
+    const char* base = reinterpret_cast<const char*>(W);
+    if constexpr (P == OK_F64) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const double2 d = *reinterpret_cast<const double2*>(base + sigma_off<P>(Vs, mi, e, s));
+            M[e] = cpx<T>{d.x, d.y};
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float4 f = *reinterpret_cast<const float4*>(base + sigma_off<P>(Vs, mi, 2 * j, s));
+            M[2 * j] = cpx<T>{f.x, f.y};
+            M[2 * j + 1] = cpx<T>{f.z, f.w};
+        }
+        const float2 f = *reinterpret_cast<const float2*>(base + sigma_off<P>(Vs, mi, 8, s));
+        M[8] = cpx<T>{f.x, f.y};
+    }
+}
+
+// y = M x (DAG: y = M^dag x) for the two spins of a pair, x[2][3] -> y[2][3]
+template <bool DAG, typename T>
+__device__ __forceinline__ void mv2(const cpx<T> M[9], const cpx<T> x[2][3], cpx<T> y[2][3]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cpx<T> acc{0, 0};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if constexpr (DAG) cfma_conj(acc, M[3 * b + a], x[sp][b]);
+                else cfma(acc, M[3 * a + b], x[sp][b]);
+            }
+            y[sp][a] = acc;
+        }
+}
+
+// o += c * sigma_n y on a spin pair (n = 0..3, uniform across the wavefront), c = +1 or -1
+template <typename T>
+__device__ __forceinline__ void sig_acc(int n, T c, const cpx<T> y[2][3], cpx<T> o[2][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cpx<T> y0 = c * y[0][a], y1 = c * y[1][a];
+        switch (n) {
+            case 0: o[0][a] = o[0][a] + y0; o[1][a] = o[1][a] + y1; break;
+            case 1: o[0][a] = o[0][a] + y1; o[1][a] = o[1][a] + y0; break;
+            case 2:   // sigma_2 = [[0, -i], [i, 0]]
+                o[0][a] = o[0][a] + cpx<T>{y1.im, -y1.re};
+                o[1][a] = o[1][a] + cpx<T>{-y0.im, y0.re};
+                break;
+            default: o[0][a] = o[0][a] + y0; o[1][a] = o[1][a] - y1; break;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero2(cpx<T> o[2][3]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[sp][a] = cpx<T>{0, 0};
+}
+
+// o += sum_{n in [n0, n0 + cnt)} sigma_n (M_{mi0 + n - n0}^(dag) x)
+template <int P, bool DAG, typename T>
+__device__ __forceinline__ void pauli_sum(const void* __restrict__ W, int Vs, int s, int mi0, int n0, int cnt, T c,
+                                          const cpx<T> x[2][3], cpx<T> o[2][3]) {
+#pragma unroll 1
+    for (int q = 0; q < cnt; ++q) {
+        cpx<T> M[9], y[2][3];
+        ld_mat<P, T>(W, Vs, mi0 + q, s, M);
+        mv2<DAG, T>(M, x, y);
+        sig_acc(n0 + q, c, y, o);
+    }
+}
+
+// acc[spin pair][spin][colour] += [[A, B], [B, A]] (u, d) with A + B = 2 sum_n sigma_n P_n,
+// A - B = 2 sum_n sigma_n Q_n, P_n / Q_n at mi (P), mi + 4 (Q); the backward block swaps and
+// daggers them.  Half h = 0: y = (A + B)(u + d) / 2 goes to both pairs; h = 1: y = (A - B)(u - d) / 2
+// to the upper pair and, negated, to the lower one.
+template <int P, bool BWD, typename T>
+__device__ __forceinline__ void hop_ds(const void* __restrict__ W, int Vs, int s, int mi, const cpx<T> v[12],
+                                       cpx<T> acc[2][2][3]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cpx<T> x[2][3], y[2][3];
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                x[sp][a] = h == 0 ? v[3 * sp + a] + v[6 + 3 * sp + a] : v[3 * sp + a] - v[6 + 3 * sp + a];
+        zero2(y);
+        pauli_sum<P, BWD, T>(W, Vs, s, (h == 0) == BWD ? mi + 4 : mi, 0, 4, T(1), x, y);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                acc[0][sp][a] = acc[0][sp][a] + y[sp][a];
+                acc[1][sp][a] = h == 0 ? acc[1][sp][a] + y[sp][a] : acc[1][sp][a] - y[sp][a];
+            }
+    }
+}
+
+// W++_ii: A = 1 (x) G0, B = sigma_i (x) G1 (G0 at mi, G1 at mi + 1); backward: G0^dag, -G1^dag
+template <int P, bool BWD, typename T>
+__device__ __forceinline__ void hop_ii(const void* __restrict__ W, int Vs, int s, int mi, int i, const cpx<T> v[12],
+                                       cpx<T> acc[2][2][3]) {
+    cpx<T> u[2][3], d[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u[sp][a] = v[3 * sp + a];
+            d[sp][a] = v[6 + 3 * sp + a];
+        }
+    const T c1 = BWD ? T(-1) : T(1);
+    cpx<T> M[9], y[2][3];
+    ld_mat<P, T>(W, Vs, mi, s, M);
+    mv2<BWD, T>(M, u, y);
+    sig_acc(0, T(1), y, acc[0]);
+    mv2<BWD, T>(M, d, y);
+    sig_acc(0, T(1), y, acc[1]);
+    ld_mat<P, T>(W, Vs, mi + 1, s, M);
+    mv2<BWD, T>(M, d, y);
+    sig_acc(1 + i, c1, y, acc[0]);
+    mv2<BWD, T>(M, u, y);
+    sig_acc(1 + i, c1, y, acc[1]);
+}
+
+// [[0, H], [H, 0]] with H = (sigma_{1+i} + sg sigma_{1+j}) (x) T (T at mi); backward: -H^dag
+template <int P, bool BWD, typename T>
+__device__ __forceinline__ void hop_off(const void* __restrict__ W, int Vs, int s, int mi, int i, int j, T sg,
+                                        const cpx<T> v[12], cpx<T> acc[2][2][3]) {
+    cpx<T> u[2][3], d[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u[sp][a] = v[3 * sp + a];
+            d[sp][a] = v[6 + 3 * sp + a];
+        }
+    const T c = BWD ? T(-1) : T(1);
+    cpx<T> M[9], y[2][3];
+    ld_mat<P, T>(W, Vs, mi, s, M);
+    mv2<BWD, T>(M, d, y);
+    sig_acc(1 + i, c, y, acc[0]);
+    sig_acc(1 + j, c * sg, y, acc[0]);
+    mv2<BWD, T>(M, u, y);
+    sig_acc(1 + i, c, y, acc[1]);
+    sig_acc(1 + j, c * sg, y, acc[1]);
+}
+
+// W+_4 = [[0, H], [H, N]], H = sum_{m=1..3} sigma_m S_m (mi .. mi + 2), N at mi + 3;
+// backward: [[N^dag, -H^dag], [-H^dag, 0]]
+template <int P, bool BWD, typename T>
+__device__ __forceinline__ void hop_t(const void* __restrict__ W, int Vs, int s, int mi, const cpx<T> v[12],
+                                      cpx<T> acc[2][2][3]) {
+    cpx<T> u[2][3], d[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u[sp][a] = v[3 * sp + a];
+            d[sp][a] = v[6 + 3 * sp + a];
+        }
+    const T c = BWD ? T(-1) : T(1);
+    pauli_sum<P, BWD, T>(W, Vs, s, mi, 1, 3, c, d, acc[0]);
+    pauli_sum<P, BWD, T>(W, Vs, s, mi, 1, 3, c, u, acc[1]);
+    cpx<T> M[9], y[2][3];
+    ld_mat<P, T>(W, Vs, mi + 3, s, M);
+    if constexpr (BWD) {
+        mv2<true, T>(M, u, y);
+        sig_acc(0, T(1), y, acc[0]);
+    } else {
+        mv2<false, T>(M, d, y);
+        sig_acc(0, T(1), y, acc[1]);
+    }
+}
+
+// W0 = [[A, B], [-B, A]]: out_u + i out_d = (A - iB)(u + i d), out_u - i out_d = (A + iB)(u - i d),
+// (A -+ iB) = 2 sum_m sigma_m R-+_m with R-_m at mi + m - 1 and R+_m at mi + 2 + m.  Half h = 0:
+// y = (A - iB)(u + i d) / 2 adds y to the upper pair and -i y to the lower; h = 1: y = (A + iB)(u - i d) / 2
+// adds y and +i y.
+template <int P, typename T>
+__device__ __forceinline__ void hop_w0(const void* __restrict__ W, int Vs, int s, int mi, const cpx<T> v[12],
+                                       cpx<T> acc[2][2][3]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cpx<T> x[2][3], y[2][3];
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const cpx<T> u = v[3 * sp + a], d = v[6 + 3 * sp + a];
+                const cpx<T> id{-d.im, d.re};
+                x[sp][a] = h == 0 ? u + id : u - id;
+            }
+        zero2(y);
+        pauli_sum<P, false, T>(W, Vs, s, mi + 3 * h, 1, 3, T(1), x, y);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const cpx<T> w = y[sp][a];
+                acc[0][sp][a] = acc[0][sp][a] + w;
+                acc[1][sp][a] = acc[1][sp][a] + (h == 0 ? cpx<T>{w.im, -w.re} : cpx<T>{-w.im, w.re});
+            }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ld_sp(const T* __restrict__ psi, int s, cpx<T> v[12]) {
+    const cpx<T>* p = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) v[q] = p[q];
+}
+
+template <int P, int EPI>
+__global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restrict__ W,
+                                                     const typename SArith<P>::T* __restrict__ psi,
+                                                     typename SArith<P>::T* __restrict__ out, double mhat_d,
+                                                     const typename SArith<P>::T* __restrict__ aux,
+                                                     double2* __restrict__ partial) {
+    using T = typename SArith<P>::T;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = s < g.V;
+    double2 d1{0.0, 0.0}, d2{0.0, 0.0};
+    if (live) {
+        const int Vs = g.Vs;
+        int x, y, z, t;
+        site_coords(g, s, x, y, z, t);
+        cpx<T> acc[2][2][3], v[12];
+        ld_sp(psi, s, v);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) acc[h][sp][a] = T(mhat_d) * v[6 * h + 3 * sp + a];
+        hop_w0<P, T>(W, Vs, s, SG_W0, v, acc);
+#pragma unroll 1
+        for (int i = 0; i < 3; ++i) {   // +-i: W+_i at x, Gamma(W+_i) at x - i
+            int n = neighbour(g, x, y, z, t, off_d(1 + i, 0), off_d(1 + i, 1), off_d(1 + i, 2), 0);
+            ld_sp(psi, n, v);
+            hop_ds<P, false, T>(W, Vs, s, SG_WI + 8 * i, v, acc);
+            n = neighbour(g, x, y, z, t, -off_d(1 + i, 0), -off_d(1 + i, 1), -off_d(1 + i, 2), 0);
+            ld_sp(psi, n, v);
+            hop_ds<P, true, T>(W, Vs, n, SG_WI + 8 * i, v, acc);
+        }
+        {   // +-t
+            int n = neighbour(g, x, y, z, t, 0, 0, 0, 1);
+            ld_sp(psi, n, v);
+            hop_t<P, false, T>(W, Vs, s, SG_W4, v, acc);
+            n = neighbour(g, x, y, z, t, 0, 0, 0, -1);
+            ld_sp(psi, n, v);
+            hop_t<P, true, T>(W, Vs, n, SG_W4, v, acc);
+        }
+#pragma unroll 1
+        for (int i = 0; i < 3; ++i) {   // +-2i
+            int n = neighbour(g, x, y, z, t, off_d(9 + i, 0), off_d(9 + i, 1), off_d(9 + i, 2), 0);
+            ld_sp(psi, n, v);
+            hop_ii<P, false, T>(W, Vs, s, SG_WII + 2 * i, i, v, acc);
+            n = neighbour(g, x, y, z, t, -off_d(9 + i, 0), -off_d(9 + i, 1), -off_d(9 + i, 2), 0);
+            ld_sp(psi, n, v);
+            hop_ii<P, true, T>(W, Vs, n, SG_WII + 2 * i, i, v, acc);
+        }
+#pragma unroll 1
+        for (int p = 0; p < 3; ++p) {   // +-(i+j) and +-(i-j)
+            const int i = p < 2 ? 0 : 1, j = p == 0 ? 1 : 2;
+            const int k1 = 15 + p, k2 = 21 + p;
+            int n = neighbour(g, x, y, z, t, off_d(k1, 0), off_d(k1, 1), off_d(k1, 2), 0);
+            ld_sp(psi, n, v);
+            hop_off<P, false, T>(W, Vs, s, SG_WIJ + p, i, j, T(1), v, acc);
+            n = neighbour(g, x, y, z, t, -off_d(k1, 0), -off_d(k1, 1), -off_d(k1, 2), 0);
+            ld_sp(psi, n, v);
+            hop_off<P, true, T>(W, Vs, n, SG_WIJ + p, i, j, T(1), v, acc);
+            n = neighbour(g, x, y, z, t, off_d(k2, 0), off_d(k2, 1), off_d(k2, 2), 0);
+            ld_sp(psi, n, v);
+            hop_off<P, false, T>(W, Vs, s, SG_WIMJ + p, i, j, T(-1), v, acc);
+            n = neighbour(g, x, y, z, t, -off_d(k2, 0), -off_d(k2, 1), -off_d(k2, 2), 0);
+            ld_sp(psi, n, v);
+            hop_off<P, true, T>(W, Vs, n, SG_WIMJ + p, i, j, T(-1), v, acc);
+        }
+        cpx<T>* o = reinterpret_cast<cpx<T>*>(out) + (size_t)s * 12;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) o[q] = acc[q / 6][(q / 3) & 1][q % 3];
+        if constexpr (EPI == EPI_RV) {
+            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(aux) + (size_t)s * 12;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const cpx<T> av = a[q], w = acc[q / 6][(q / 3) & 1][q % 3];
+                d1.x += (double)av.re * w.re + (double)av.im * w.im;
+                d1.y += (double)av.re * w.im - (double)av.im * w.re;
+            }
+        } else if constexpr (EPI == EPI_TS) {
+            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const cpx<T> sv = a[q], w = acc[q / 6][(q / 3) & 1][q % 3];
+                d1.x += (double)w.re * sv.re + (double)w.im * sv.im;
+                d1.y += (double)w.re * sv.im - (double)w.im * sv.re;
+                d2.x += (double)w.re * w.re + (double)w.im * w.im;
+            }
+        }
+    }
+    if constexpr (EPI != EPI_NONE) block_reduce2_store(d1, d2, partial);
+}
+
+template <int P>
+int launch_sigma_t(const Geo& g, const void* W, const void* psi, void* out, double mhat, int epi, const void* aux,
+                   double2* partial, hipStream_t st) {
+    using T = typename SArith<P>::T;
+    const unsigned nb = grid_for(g.V, 256);
+    const T* in = reinterpret_cast<const T*>(psi);
+    T* o = reinterpret_cast<T*>(out);
+    const T* ax = reinterpret_cast<const T*>(aux);
+    if (epi == EPI_NONE) k_apply_sigma<P, EPI_NONE><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
+    else if (epi == EPI_RV) k_apply_sigma<P, EPI_RV><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
+    else k_apply_sigma<P, EPI_TS><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
+    OK_LAUNCH_CHECK("k_apply_sigma");
+    return OK_SUCCESS;
+}
+
+}  // namespace
+
+int launch_apply_sigma(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int epi,
+                       const void* aux, double2* partial, hipStream_t st) {
+    if ((Wprec & 3) == OK_F64) return launch_sigma_t<OK_F64>(g, W, psi, out, mhat, epi, aux, partial, st);
+    return launch_sigma_t<OK_F32>(g, W, psi, out, mhat, epi, aux, partial, st);
+}
+
+}  // namespace okinv

@@ -19,6 +19,16 @@
 // order in which the lanes of the FP32 MFMA read their A operands, and BF16
 // blocks row-major (the BF16 MFMA reads 4 consecutive columns per lane).
 //
+// With OK_LAYOUT_SIGMA (FP64 or FP32) each forward block is kept as the colour matrices of
+// its Pauli decomposition, 46 per site (listed below), and every block is formed where
+// it is used.  Matrix mi of site s, entry e = 3a + b (row a, column b), is at
+//
+//     FP64:  double2 cell (mi * 9 + e) * Vs + s
+//     FP32:  e < 8: half e % 2 of float4 cell (mi * 4 + e / 2) * Vs + s;
+//            e = 8: float2 cell mi * Vs + s of a second region after the 46 * 4 float4 planes
+//
+// so that a wavefront of consecutive sites reads each piece of a matrix contiguously.
+//
 // With OK_LAYOUT_SAVED only the 14 blocks of the forward offsets (k = 0, +mu,
 // +2i, +i+j, +i-j: the saved set of Eq. FinalForm) are stored, plane-major as
 // above with the saved index ks in place of k; a backward block is formed
@@ -61,8 +71,30 @@ __host__ __device__ constexpr int saved_index(int k) {
 static_assert(saved_k(13) == 23 && saved_index(23) == 13 && saved_index(9) == 5 && saved_index(15) == 8 &&
               saved_index(26) == -1 && saved_k(5) == 9, "saved set");
 
+// Pauli-decomposed forward blocks (layout LAY_SIGMA): W = [[A, B], [C, D]] in 2x2 spin blocks,
+// each a sum_n sigma_n (x) X_n over n = 0..3 (sigma_0 = 1).  Colour matrices kept per site:
+//   W0      [[H1, H2], [-H2, H1]]:  (X1_m - i X2_m) / 2, then (X1_m + i X2_m) / 2, m = 1..3  (mi 0..5)
+//   W+_i    [[H1, H2], [H2, H1]]:   P_n = (X1_n + X2_n) / 2, then Q_n = (X1_n - X2_n) / 2    (mi 6 + 8i ..)
+//   W+_4    [[0, H1], [H1, H2]]:    X1_1..3, then X2_0 (= -U_4)                              (mi 30..33)
+//   W++_ii  [[H1, H2], [H2, H1]]:   X1_0, X2_i                                               (mi 34 + 2i ..)
+//   W++_ij  [[0, H1], [H1, 0]]:     X1_i (H1 = (sigma_i + sigma_j) X1_i)                     (mi 40 + p)
+//   W+-_ij  [[0, H1], [H1, 0]]:     X1_i (H1 = (sigma_i - sigma_j) X1_i)                     (mi 43 + p)
+// (X1, X2: the components of H1, H2; p = 0, 1, 2 for (i, j) = (x, y), (x, z), (y, z).)
+constexpr int LAY_SIGMA = 3;
+constexpr int kSigma = 46;
+constexpr int SG_W0 = 0, SG_WI = 6, SG_W4 = 30, SG_WII = 34, SG_WIJ = 40, SG_WIMJ = 43;
+
 inline int layout_of(int prec) {
-    return (prec & OK_LAYOUT_SITE) ? LAY_SITE : (prec & OK_LAYOUT_SAVED) ? LAY_SAVED : LAY_PLANE;
+    return (prec & OK_LAYOUT_SITE) ? LAY_SITE : (prec & OK_LAYOUT_SAVED) ? LAY_SAVED
+         : (prec & OK_LAYOUT_SIGMA) ? LAY_SIGMA : LAY_PLANE;
+}
+
+// byte offset of entry e of colour matrix mi at site s (LAY_SIGMA; P = OK_F64 or OK_F32)
+template <int P>
+__host__ __device__ __forceinline__ size_t sigma_off(int Vs, int mi, int e, int s) {
+    if constexpr (P == OK_F64) return ((size_t)(mi * 9 + e) * Vs + s) * 16;
+    if (e < 8) return ((size_t)(mi * 4 + e / 2) * Vs + s) * 16 + (size_t)(e & 1) * 8;
+    return (size_t)kSigma * 4 * Vs * 16 + ((size_t)mi * Vs + s) * 8;
 }
 
 __host__ __device__ __forceinline__ size_t w_cell(int layout, int Vs, int ch, int k, int j, int s) {
@@ -73,6 +105,7 @@ __host__ __device__ __forceinline__ size_t w_cell(int layout, int Vs, int ch, in
 
 inline size_t w_bytes(int prec, int Vs, int layout = LAY_PLANE) {
     size_t es = prec == OK_F64 ? 16 : prec == OK_F32 ? 8 : 4;
+    if (layout == LAY_SIGMA) return (size_t)kSigma * 9 * es * (size_t)Vs;
     return (size_t)(layout == LAY_SAVED ? kSaved : kW) * kWE * es * (size_t)Vs;
 }
 

@@ -23,6 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 OK_F64, OK_F32, OK_BF16 = 0, 1, 2
 OK_LAYOUT_SITE = 0x10
 OK_LAYOUT_SAVED = 0x100
+OK_LAYOUT_SIGMA = 0x200
 OK_SPINOR_RHS_INNER = 0x20
 OK_NET_ADJOINT = 0x40
 OK_NET_MAX_LAYERS = 16
@@ -44,7 +45,7 @@ class ok_coeffs(C.Structure):
 class ok_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("delta", C.c_double), ("max_iter", C.c_int32),
                 ("max_restarts", C.c_int32), ("zero_guess", C.c_int32), ("verbose", C.c_int32),
-                ("stall_window", C.c_int32)]
+                ("stall_window", C.c_int32), ("W64_layout", C.c_int32)]
 
 
 class ok_solver_stats(C.Structure):
@@ -199,10 +200,11 @@ class SolverParams:
     zero_guess: int = 1
     verbose: int = 0
     stall_window: int = 0
+    W64_layout: int = 0
 
     def c(self):
         return ok_solver_params(self.tol, self.delta, self.max_iter, self.max_restarts,
-                                self.zero_guess, self.verbose, self.stall_window)
+                                self.zero_guess, self.verbose, self.stall_window, self.W64_layout)
 
 
 def ok_bicgstab(dims, c, params, d_W64, d_Wlo, Wlo_prec, d_xi, d_psi, nrhs, d_work, stream=None, net=None):

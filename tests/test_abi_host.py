@@ -37,7 +37,7 @@ def test_binding_covers_header():
 
 def test_abi_version():
     from paper_1311_5029_amd import okinv
-    assert okinv.ok_abi_version() == 2
+    assert okinv.ok_abi_version() == 3
 
 
 def test_saved_layout_size_and_flags():
@@ -49,6 +49,19 @@ def test_saved_layout_size_and_flags():
     with pytest.raises(okinv.OkError) as e:
         okinv.ok_W_bytes(dims, okinv.OK_F32 | okinv.OK_LAYOUT_SAVED | okinv.OK_LAYOUT_SITE)
     assert e.value.status == okinv.OK_EINVAL
+
+
+def test_sigma_layout_size_and_flags():
+    from paper_1311_5029_amd import okinv
+    dims = (5, 6, 7, 3)
+    for prec in (okinv.OK_F64, okinv.OK_F32):
+        full = okinv.ok_W_bytes(dims, prec)
+        assert okinv.ok_W_bytes(dims, prec | okinv.OK_LAYOUT_SIGMA) * 27 * 144 == full * 46 * 9
+    for bad in (okinv.OK_BF16 | okinv.OK_LAYOUT_SIGMA, okinv.OK_F32 | okinv.OK_LAYOUT_SIGMA | okinv.OK_LAYOUT_SITE,
+                okinv.OK_F64 | okinv.OK_LAYOUT_SIGMA | okinv.OK_LAYOUT_SAVED):
+        with pytest.raises(okinv.OkError) as e:
+            okinv.ok_W_bytes(dims, bad)
+        assert e.value.status == okinv.OK_EINVAL
 
 
 def test_size_queries():
@@ -162,6 +175,14 @@ def test_solver_validation_before_device():
     assert lib.ok_bicgstab(*args(good, need3, 0x50000000, okinv.OK_F32, ctypes.byref(bad_net))) == okinv.OK_EINVAL
     bad = okinv.SolverParams(stall_window=-1).c()
     assert lib.ok_bicgstab(*args(bad, need2, 0x50000000, okinv.OK_F32)) == okinv.OK_EINVAL
+    # W64 layout: 0, saved or sigma only; low-precision sigma W only in FP32, one layout flag
+    bad = okinv.SolverParams(W64_layout=okinv.OK_LAYOUT_SITE).c()
+    assert lib.ok_bicgstab(*args(bad, need)) == okinv.OK_EINVAL
+    for wlo in (okinv.OK_BF16 | okinv.OK_LAYOUT_SIGMA, okinv.OK_F32 | okinv.OK_LAYOUT_SIGMA | okinv.OK_LAYOUT_SITE):
+        assert lib.ok_bicgstab(*args(good, need2, 0x50000000, wlo)) == okinv.OK_EINVAL
+        with pytest.raises(okinv.OkError):
+            okinv.ok_bicgstab_workspace_bytes(dims, 1, wlo)
+    assert okinv.ok_bicgstab_workspace_bytes(dims, 1, okinv.OK_F32 | okinv.OK_LAYOUT_SIGMA) == need2
 
 
 def test_net_sizes_and_validation_before_device():

@@ -201,6 +201,63 @@ def test_apply_saved_layout_matches_oracle(lat, prec):
     assert rel(got, lat.apply(prec, psi)) <= (1e-14 if prec == 0 else 1e-6 if prec == 1 else 1e-5)
 
 
+SIGMA = 0x200   # OK_LAYOUT_SIGMA
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_sigma_layout_expands_to_oracle_blocks(lat, prec):
+    """The 46 Pauli-component colour matrices per site expand to the oracle's 27 dense blocks:
+    FP64 to 1e-13 of max|W|; FP32 within a few roundings (an entry is a sum of at most four
+    stored FP32 values, each within 2^-24 of its own magnitude)."""
+    got = lat.dense_W(prec | SIGMA)
+    ref = lat.oracle_W
+    m = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= (1e-13 if prec == 0 else 2.0 ** -21) * m
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_apply_sigma_layout_matches_oracle(lat, prec):
+    psi = I.gaussian_sources(lat.dims, 2, 28)
+    ref = lat.oracle_B.apply(psi)
+    got = lat.apply(prec | SIGMA, psi)
+    tol = TOL_APPLY[prec]
+    assert rel(got, ref) <= tol
+    assert maxrel(got, ref) <= tol * (1.0 if prec == 0 else 3.0)
+    assert rel(got, lat.apply(prec, psi)) <= (1e-14 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 3, 5), (4, 4, 3, 4), (3, 3, 3, 3)], ids=["3x4x3x5", "4x4x3x4", "3^4"])
+def test_apply_sigma_small_lattices(dims):
+    """L = 3 and 4: coinciding offsets and backward blocks read at the site itself or at a
+    coinciding neighbour still add up to M (FP64 and FP32)."""
+    ok = lib()
+    U, c = make(dims, seed=9)
+    L = Lattice(dims, U, c)
+    psi = I.gaussian_sources(dims, 1, 29)[0]
+    ref = OKOperatorB(U, c).apply(psi)
+    assert rel(L.apply(ok.OK_F64 | SIGMA, psi), ref) < 1e-12
+    assert rel(L.apply(ok.OK_F32 | SIGMA, psi.astype(np.complex64)), ref) < 1e-6
+
+
+def test_free_field_plane_wave_sigma():
+    """Unit links: the sigma-layout operator on a plane wave is the closed-form momentum-space
+    symbol (FP64)."""
+    ok = lib()
+    from oracle.free import symbol_matrix
+    dims = (5, 6, 4, 7)
+    c = I.standin_coeffs(u0=0.91)
+    L = Lattice(dims, I.unit_links(dims), c)
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx), indexing="ij")
+    n = (1, 2, 3, 2)
+    k = [2 * np.pi * n[m] / dims[m] for m in range(4)]
+    ph = np.exp(1j * (k[0] * x + k[1] * y + k[2] * z + k[3] * t))
+    chi = np.arange(12).reshape(4, 3) * (1 - 0.5j) + 0.25
+    got = L.apply(ok.OK_F64 | SIGMA, ph[..., None, None] * chi)
+    want = ph[..., None, None] * (symbol_matrix(k, c) @ chi)
+    assert rel(got, want) < 1e-13
+
+
 @pytest.mark.parametrize("dims", [(3, 4, 3, 5), (4, 4, 3, 4)], ids=["3x4x3x5", "4x4x3x4"])
 def test_apply_saved_small_lattices(dims):
     """L = 3 and 4: the forward block read for a backward offset may be the site's own or a
@@ -251,8 +308,9 @@ def big():
     return L
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 0x100, 0x101, 0x102],
-                         ids=["f64", "f32", "bf16", "f64-saved", "f32-saved", "bf16-saved"])
+@pytest.mark.parametrize("prec", [0, 1, 2, 0x100, 0x101, 0x102, 0x200, 0x201],
+                         ids=["f64", "f32", "bf16", "f64-saved", "f32-saved", "bf16-saved", "f64-sigma",
+                              "f32-sigma"])
 def test_full_size_sampled_sites(big, prec):
     """Sampled sites of M psi at 20^3 x 64 against the oracle evaluated site by site."""
     psi = I.gaussian_sources(big.dims, 1, 31)[0]
@@ -288,6 +346,7 @@ def test_full_size_gamma5_hermiticity(big):
     from oracle.basis import GAMMA5
     phi, psi = I.gaussian_sources(big.dims, 2, 32)
     g5 = lambda f: GAMMA5 @ f
-    a = np.vdot(phi, g5(big.apply(ok.OK_F64, g5(psi))))
-    b = np.vdot(big.apply(ok.OK_F64, phi), psi)
-    assert abs(a - b) / abs(b) < 1e-12
+    for prec in (ok.OK_F64, ok.OK_F64 | SIGMA):
+        a = np.vdot(phi, g5(big.apply(prec, g5(psi))))
+        b = np.vdot(big.apply(prec, phi), psi)
+        assert abs(a - b) / abs(b) < 1e-12

@@ -23,7 +23,8 @@ TOL = 1e-10
 ORACLE_SLACK = 1.05
 
 
-def solve(L, xi, low=None, params=None, guess=None, net=None):
+def solve(L, xi, low=None, params=None, guess=None, net=None, w64=0):
+    """w64: layout flag of the FP64 W (0, OK_LAYOUT_SAVED or OK_LAYOUT_SIGMA)."""
     ok = L.ok
     torch = L.torch
     nrhs = xi.shape[0] if xi.ndim == 7 else 1
@@ -31,9 +32,10 @@ def solve(L, xi, low=None, params=None, guess=None, net=None):
     psi = ok.to_device_complex(guess) if guess is not None else torch.zeros_like(d_xi)
     lo_prec = -1 if low is None else low
     work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(L.dims, nrhs, lo_prec, net))
-    W64 = L.precompute(ok.OK_F64)
+    W64 = L.precompute(ok.OK_F64 | w64)
     Wlo = None if low is None else L.precompute(low)
     p = params or ok.SolverParams(tol=TOL)
+    p.W64_layout = w64
     if guess is not None:
         p.zero_guess = 0
     rc, st = ok.ok_bicgstab(L.dims, L.c, p, W64, Wlo, lo_prec, d_xi, psi, nrhs, work, net=net)
@@ -343,3 +345,49 @@ def test_batched_with_network_two_groups(learned_small):
         if k != 7:
             assert st[k]["fallbacks"] == 0 and st[k]["net_applies"] > 0
             assert oracle_resid(L.U, L.c, xi[k], x[k]) <= ORACLE_SLACK * TOL
+
+
+# --- compact W layouts in the solver ---------------------------------------------------------
+SAVED, SIGMA = 0x100, 0x200
+
+
+@pytest.fixture(scope="module")
+def mid():
+    dims = (6, 6, 6, 8)
+    cfg = I.make_config("mixed_16x16x16x32", dims=dims)
+    L = Lattice(dims, cfg["U"], cfg["coeffs"])
+    L.xi = I.gaussian_sources(dims, 3, 76)
+    return L
+
+
+@pytest.mark.parametrize("w64,low", [(SIGMA, None), (SAVED, None), (SIGMA, 1 | SIGMA), (SAVED, 2 | SAVED),
+                                     (SIGMA, 1), (SIGMA, 2 | 0x10)],
+                         ids=["plain-sigma", "plain-saved", "f32-sigma", "bf16-saved", "f32-dense-lo", "batched-bf16"])
+def test_compact_layouts_in_solver(mid, w64, low):
+    """Plain, mixed and batched solves with the FP64 (and low-precision) operator in the saved or
+    sigma layout reach the oracle's residual bound in about as many iterations as with 27 dense
+    blocks (the same operator up to rounding)."""
+    ok = lib()
+    L = mid
+    dense_low = None if low is None else low & ~(SAVED | SIGMA)
+    xi = L.xi if (low or 0) & 0x10 else L.xi[0]
+    rc0, st0, _ = solve(L, xi, low=dense_low)
+    rc1, st1, x = solve(L, xi, low=low, w64=w64)
+    assert rc0 == rc1 == ok.OK_SUCCESS
+    xs, xis = (x, xi) if xi.ndim == 7 else (x[None], xi[None])
+    for k in range(len(st1)):
+        assert abs(st1[k]["iterations"] - st0[k]["iterations"]) <= 0.1 * st0[k]["iterations"] + 3
+        assert oracle_resid(L.U, L.c, xis[k], xs[k]) <= ORACLE_SLACK * TOL
+
+
+def test_16x16x16x32_sigma_layout_full_size():
+    """The 16^3 x 32 workload with the FP64 and FP32 operators in the sigma layout: plain FP64 and
+    FP32 + FP64 reliable updates both reach the oracle's residual bound."""
+    ok = lib()
+    cfg = I.make_config("mixed_16x16x16x32")
+    L = Lattice(cfg["dims"], cfg["U"], cfg["coeffs"])
+    xi = cfg["xi"][0]
+    for low in (None, ok.OK_F32 | SIGMA):
+        rc, st, x = solve(L, xi, low=low, w64=SIGMA)
+        assert rc == ok.OK_SUCCESS
+        assert oracle_resid(cfg["U"], cfg["coeffs"], xi, x) <= ORACLE_SLACK * TOL
