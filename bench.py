@@ -54,7 +54,7 @@ def log(msg):
 def source_hash(kernel="k_apply"):
     """Hash of the sources of a kernel (its file plus the shared layout headers)."""
     h = hashlib.sha256()
-    main = "stencil.hip" if kernel == "k_apply" else "stencil_mrhs.hip"
+    main = {"k_apply": "stencil.hip", "k_apply_sigma": "stencil_sigma.hip"}.get(kernel, "stencil_mrhs.hip")
     for f in (main, "wlayout.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1311_5029_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -91,6 +91,8 @@ def is_apply_kernel(name, form, kernel="k_apply"):
         return ("k_apply_site<%d, 1>" % p) in name or ("k_apply_siteILi%dELi1E" % p) in name
     if kernel == "k_apply_mrhs":
         return ("k_apply_mrhs<%d>" % p) in name or ("k_apply_mrhsILi%dE" % p) in name
+    if kernel in ("k_apply_saved", "k_apply_sigma"):   # <prec, no epilogue>
+        return ("%s<%d, 0>" % (kernel, p)) in name or ("%sILi%dELi0E" % (kernel, p)) in name
     return any(("k_apply<%d, %d, 0>" % (p, t)) in name or ("k_applyILi%dELi%dELi0E" % (p, t)) in name
                for t in (1, 2, 4))
 
@@ -129,9 +131,9 @@ def parse_pmc(fetch_dir, write_dir, form):
     summary per kernel found (consumed by the benchmark's roofline entry)."""
     prec = {"f64": 0, "f32": 1, "bf16": 2}[form]
     algo = {"k_apply": BYTES_SITE[prec] * V, "k_apply_mrhs": BYTES_STEP[prec] * V,
-            "k_apply_site": BYTES_STEP[prec] * V}
+            "k_apply_site": BYTES_STEP[prec] * V, "k_apply_sigma": BYTES_SIGMA.get(prec, 0) * V}
     rows = {c: _read_counters(d) for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
-    for kernel in ("k_apply", "k_apply_mrhs", "k_apply_site"):
+    for kernel in ("k_apply", "k_apply_mrhs", "k_apply_site", "k_apply_sigma"):
         res = {}
         for cname in ("FETCH_SIZE", "WRITE_SIZE"):
             ker = [v[cname] for (k, _), v in rows[cname].items() if cname in v and is_apply_kernel(k, form, kernel)]
@@ -168,8 +170,11 @@ def summarize_trace(d, out_path, command):
         name = r["Name"].replace("okinv::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
         name = re.sub(r"\(.*", "", name).replace("void ", "")[:44]
         lines.append("%-44s %6s %14.0f %8.2f" % (name, r["Calls"], float(r["AverageNs"]), float(r["Percentage"])))
-    for kernel, per_site in (("k_apply", BYTES_SITE), ("k_apply_site", BYTES_STEP)):
+    for kernel, per_site in (("k_apply", BYTES_SITE), ("k_apply_site", BYTES_STEP), ("k_apply_saved", BYTES_SAVED),
+                             ("k_apply_sigma", BYTES_SIGMA)):
         for form, prec in (("f64", 0), ("f32", 1), ("bf16", 2)):
+            if prec not in per_site:
+                continue
             for r in rows:
                 if is_apply_kernel(r["Name"], form, kernel):
                     ns = float(r["AverageNs"])
@@ -177,7 +182,7 @@ def summarize_trace(d, out_path, command):
                     lines.append("")
                     lines.append("%s<%s> (%s): average %.0f ns per launch -> %.1f GB/s algorithmic "
                                  "(%d B/site x %d sites), %.1f%% of 8 TB/s"
-                                 % (kernel, form, "1 RHS" if kernel == "k_apply" else "12 RHS", ns, gbs,
+                                 % (kernel, form, "12 RHS" if kernel == "k_apply_site" else "1 RHS", ns, gbs,
                                     per_site[prec], V, gbs / HBM_PEAK_GBS * 100))
                     break
     with open(out_path, "w") as fh:

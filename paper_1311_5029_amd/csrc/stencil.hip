@@ -88,7 +88,8 @@ __global__ void __launch_bounds__(256) k_apply(Geo g, const void* __restrict__ W
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int grp = lane / SPW;              // row group of this lane
-    const int s = (blockIdx.x * (blockDim.x >> 6) + wave) * SPW + (lane % SPW);
+    // contiguous site ranges per XCD: neighbour spinors are shared within one L2
+    const int s = (xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave) * SPW + (lane % SPW);
     const bool live = s < g.V;
     const int r0 = grp * RPT;
     const T mhat = (T)mhat_d;
@@ -205,7 +206,8 @@ __global__ void __launch_bounds__(256) k_apply_saved(Geo g, const void* __restri
                                                      const typename Arith<P>::T* __restrict__ aux,
                                                      double2* __restrict__ partial) {
     using T = typename Arith<P>::T;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    // contiguous site ranges per XCD: the forward blocks reread as backward blocks stay in L2
+    const int s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool live = s < g.V;
     double2 d1{0.0, 0.0}, d2{0.0, 0.0};
     if (live) {
@@ -308,7 +310,7 @@ __global__ void __launch_bounds__(256) k_apply_m64(Geo g, const void* __restrict
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int grp = lane / SPW;
-    const int s = (blockIdx.x * (blockDim.x >> 6) + wave) * SPW + (lane % SPW);
+    const int s = (xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave) * SPW + (lane % SPW);
     if (s >= g.V) return;
     const int r0 = grp * RPT;
     int x, y, z, t;

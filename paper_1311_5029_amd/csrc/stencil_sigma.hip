@@ -254,7 +254,9 @@ __global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restri
                                                      const typename SArith<P>::T* __restrict__ aux,
                                                      double2* __restrict__ partial) {
     using T = typename SArith<P>::T;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    // each XCD takes a contiguous range of sites, so that the matrices a site's neighbours
+    // read again as their backward blocks are still in that XCD's L2
+    const int s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool live = s < g.V;
     double2 d1{0.0, 0.0}, d2{0.0, 0.0};
     if (live) {
