@@ -225,6 +225,25 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
                 const double* d_xi, double* d_psi, int nrhs,
                 void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream);
 
+/* Workspace bytes of ok_cgnr (six FP64 fields and the reduction scratch). */
+int ok_cgnr_workspace_bytes(const ok_geom* g, int nrhs, size_t* bytes);
+
+/* Solve M psi = xi for nrhs right-hand sides, one after the other, by CG on
+ * the normal equations M^dag M psi = M^dag xi (the M^dag M route the paper
+ * lists under Future Work), with M^dag = gamma5 M gamma5 (Eq. conjugate makes
+ * M gamma5-hermitian; gamma5 = [[0, -i], [i, 0]] on the spin pairs (0, 1),
+ * (2, 3)).  FP64 throughout; d_W64 in the layout params->W64_layout.  The
+ * recurrence keeps r = xi - M psi, so the stopping test is the same as
+ * ok_bicgstab's: the FP64 true residual ||xi - M psi|| / ||xi|| <= params->tol,
+ * checked by recomputing r when the recurrence reaches it (restarting from it
+ * if not, at most params->max_restarts times).  Each iteration applies M
+ * twice (to p and to gamma5 r).  params->delta, stall_window are unused.
+ * Arrays, ownership, statuses and synchronous behaviour as ok_bicgstab; the
+ * workspace has ok_cgnr_workspace_bytes bytes. */
+int ok_cgnr(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p, const void* d_W64,
+            const double* d_xi, double* d_psi, int nrhs, void* d_work, size_t work_bytes,
+            ok_solver_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------ learned preconditioner
  *
  * Not part of the paper's method: a gauge-covariant linear stencil network N,

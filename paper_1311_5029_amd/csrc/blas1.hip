@@ -151,6 +151,68 @@ __global__ void __launch_bounds__(BS) k_zero(int n, T* dst) {
     for (int c = 0; c < 12; ++c) st(dst, (size_t)s * 12 + c, cpx<T>{(T)0, (T)0});
 }
 
+// ---- CG on the normal equations M^dag M x = M^dag xi (M^dag = gamma5 M gamma5) ----------
+// gamma5 = [[0, -i], [i, 0]] on the upper (spins 0, 1) and lower (spins 2, 3) spin pairs:
+// (gamma5 psi)_u = -i psi_d, (gamma5 psi)_d = i psi_u.
+__device__ __forceinline__ double2 g5_comp(const double2* f, size_t site, int c) {
+    const double2 o = f[site * 12 + (c + 6) % 12];
+    return c < 6 ? make_double2(o.y, -o.x) : make_double2(-o.y, o.x);   // -i o  |  i o
+}
+
+// g = gamma5 r ; partial (0, ||r||^2)
+__global__ void __launch_bounds__(BS) k_cg_gamma5(int n, double2* g, const double2* r, double2* partial) {
+    const int s = blockIdx.x * BS + threadIdx.x;
+    double2 d{0, 0};
+    if (s < n) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double2 v = r[(size_t)s * 12 + c];
+            d.x += v.x * v.x + v.y * v.y;
+            g[(size_t)s * 12 + c] = g5_comp(r, s, c);
+        }
+    }
+    block_reduce2_store(double2{0, 0}, d, partial);
+}
+
+// x += alpha p ; r -= alpha w ; g = gamma5 r ; partial (0, ||r||^2)   (alpha real)
+__global__ void __launch_bounds__(BS) k_cg_xr(int n, double2* x, double2* r, const double2* p, const double2* w,
+                                              double2* g, const Scal* sc, double2* partial) {
+    const int s = blockIdx.x * BS + threadIdx.x;
+    double2 d{0, 0};
+    if (s < n) {
+        const double a = sc->alpha.x;
+        double2 rn[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const size_t i = (size_t)s * 12 + c;
+            const double2 pv = p[i], wv = w[i], xv = x[i], rv = r[i];
+            x[i] = make_double2(fma(a, pv.x, xv.x), fma(a, pv.y, xv.y));
+            rn[c] = make_double2(fma(-a, wv.x, rv.x), fma(-a, wv.y, rv.y));
+            r[i] = rn[c];
+            d.x += rn[c].x * rn[c].x + rn[c].y * rn[c].y;
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double2 o = rn[(c + 6) % 12];
+            g[(size_t)s * 12 + c] = c < 6 ? make_double2(o.y, -o.x) : make_double2(-o.y, o.x);
+        }
+    }
+    block_reduce2_store(double2{0, 0}, d, partial);
+}
+
+// p = gamma5 z' + beta p   (beta real; z' = M gamma5 r, so gamma5 z' = M^dag r)
+__global__ void __launch_bounds__(BS) k_cg_p(int n, double2* p, const double2* zp, const Scal* sc) {
+    const int s = blockIdx.x * BS + threadIdx.x;
+    if (s >= n) return;
+    const double b = sc->beta.x;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const size_t i = (size_t)s * 12 + c;
+        const double2 z = g5_comp(zp, s, c), pv = p[i];
+        p[i] = make_double2(fma(b, pv.x, z.x), fma(b, pv.y, z.y));
+    }
+}
+
 // One block: fixed-order reduction of nb partial pairs, then the scalar update.
 __global__ void __launch_bounds__(BS) k_finish(int kind, int nb, const double2* partial, Scal* sc) {
     double2 d1{0, 0}, d2{0, 0};
@@ -212,6 +274,36 @@ __global__ void __launch_bounds__(BS) k_finish(int kind, int nb, const double2* 
             S.omega = make_double2(1.0, 0.0);
             S.beta = make_double2(0.0, 0.0);
             S.flags = 0;
+            break;
+        }
+        case FIN_CG_INIT: {   // d2.x = ||M^dag r||^2
+            S.rho = make_double2(d2.x, 0.0);
+            S.beta = make_double2(0.0, 0.0);
+            S.flags = 0;
+            break;
+        }
+        case FIN_CG_ALPHA: {   // d2.x = ||M p||^2
+            S.tt = d2.x;
+            if (!(d2.x > tiny)) {
+                S.flags |= 1;
+                S.alpha = make_double2(0.0, 0.0);
+            } else {
+                S.alpha = make_double2(S.rho.x / d2.x, 0.0);
+            }
+            break;
+        }
+        case FIN_CG_BETA: {   // d2.x = ||M^dag r||^2 of the new residual
+            if (!(S.rho.x > tiny)) {
+                S.flags |= 1;
+                S.beta = make_double2(0.0, 0.0);
+            } else {
+                S.beta = make_double2(d2.x / S.rho.x, 0.0);
+            }
+            S.rho = make_double2(d2.x, 0.0);
+            break;
+        }
+        case FIN_CG_RR: {
+            S.rr = d2.x;
             break;
         }
         default: {   // FIN_TRUE
@@ -299,6 +391,29 @@ int launch_zero(const Geo& g, bool f64, void* dst, hipStream_t st) {
     if (f64) k_zero<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(dst));
     else k_zero<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(dst));
     OK_LAUNCH_CHECK("k_zero");
+    return OK_SUCCESS;
+}
+
+int launch_cg_gamma5(const Geo& g, double* out, const double* r, double2* partial, hipStream_t st) {
+    k_cg_gamma5<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, reinterpret_cast<double2*>(out),
+                                                   reinterpret_cast<const double2*>(r), partial);
+    OK_LAUNCH_CHECK("k_cg_gamma5");
+    return OK_SUCCESS;
+}
+
+int launch_cg_xr(const Geo& g, double* x, double* r, const double* p, const double* w, double* gr, const Scal* sc,
+                 double2* partial, hipStream_t st) {
+    k_cg_xr<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, reinterpret_cast<double2*>(x), reinterpret_cast<double2*>(r),
+                                               reinterpret_cast<const double2*>(p), reinterpret_cast<const double2*>(w),
+                                               reinterpret_cast<double2*>(gr), sc, partial);
+    OK_LAUNCH_CHECK("k_cg_xr");
+    return OK_SUCCESS;
+}
+
+int launch_cg_p(const Geo& g, double* p, const double* zp, const Scal* sc, hipStream_t st) {
+    k_cg_p<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, reinterpret_cast<double2*>(p), reinterpret_cast<const double2*>(zp),
+                                              sc);
+    OK_LAUNCH_CHECK("k_cg_p");
     return OK_SUCCESS;
 }
 

@@ -95,7 +95,16 @@ int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, co
                      const void* t, const void* rhat, const Scal* sc, double2* partial, hipStream_t st);
 int launch_dot_rr(const Geo& g, bool f64, const void* rhat, const void* r, double2* partial, hipStream_t st);
 int launch_finish(int kind, int nblocks, const double2* partial, Scal* sc, hipStream_t st);
-enum Finish { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_RHO_REPLACE = 3, FIN_INIT = 4, FIN_TRUE = 5 };
+enum Finish { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_RHO_REPLACE = 3, FIN_INIT = 4, FIN_TRUE = 5,
+              FIN_CG_INIT = 6, FIN_CG_ALPHA = 7, FIN_CG_BETA = 8, FIN_CG_RR = 9 };
+// CG on M^dag M (FP64 fields; M^dag = gamma5 M gamma5):
+//   out = gamma5 r, partial ||r||^2
+int launch_cg_gamma5(const Geo& g, double* out, const double* r, double2* partial, hipStream_t st);
+//   x += alpha p ; r -= alpha w ; gr = gamma5 r ; partial ||r||^2
+int launch_cg_xr(const Geo& g, double* x, double* r, const double* p, const double* w, double* gr, const Scal* sc,
+                 double2* partial, hipStream_t st);
+//   p = gamma5 zp + beta p
+int launch_cg_p(const Geo& g, double* p, const double* zp, const Scal* sc, hipStream_t st);
 // r64 = xi - t64; optionally rlo = (float) r64; partial <r64, r64>
 int launch_residual(const Geo& g, const double* xi, const double* t64, double* r64, float* rlo,
                     double2* partial, hipStream_t st);

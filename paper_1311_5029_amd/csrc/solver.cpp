@@ -225,6 +225,84 @@ int solve_plain(Ctx& C, const double* xi, double* x, ok_solver_stats* S) {
     }
 }
 
+// CG on the normal equations M^dag M x = M^dag xi with M^dag = gamma5 M gamma5 (Eq. conjugate makes M
+// gamma5-hermitian), in the residual form that keeps r = xi - M x: with z = M^dag r,
+//   alpha = |z|^2 / |M p|^2 ; x += alpha p ; r -= alpha M p ; beta = |z_new|^2 / |z|^2 ; p = z_new + beta p.
+// z is formed as gamma5 (M (gamma5 r)); |z| = |M gamma5 r| since gamma5 is unitary.
+// FP64 fields r p w g z' t = C.w.f64[0..5].
+int cg_start(Ctx& C, double* r, double* p, double* g, double* zp) {
+    OK_TRY(launch_cg_gamma5(C.g, g, r, C.w.partial, C.st));
+    OK_TRY(fin_blas(C, FIN_CG_RR));
+    OK_TRY(launch_apply(C.g, C.W64, C.W64_prec, g, zp, C.c->mhat, C.tps64, EPI_TS, nullptr, C.w.partial, C.st));
+    OK_TRY(fin(C, FIN_CG_INIT, apply_blocks(C.g, C.tps64)));
+    OK_TRY(launch_zero(C.g, true, p, C.st));
+    return launch_cg_p(C.g, p, zp, C.w.sc, C.st);
+}
+
+int solve_cgnr(Ctx& C, const double* xi, double* x, ok_solver_stats* S) {
+    const ok_solver_params& P = *C.p;
+    double* r = C.w.f64[0];
+    double* p = C.w.f64[1];
+    double* w = C.w.f64[2];
+    double* g = C.w.f64[3];
+    double* zp = C.w.f64[4];
+    double* t = C.w.f64[5];
+    double xn;
+    OK_TRY(source_norm(C, xi, &xn));
+    if (!std::isfinite(xn)) {
+        set_error("source is not finite");
+        return S->status = OK_ENONFINITE;
+    }
+    if (xn == 0.0) {
+        OK_TRY(launch_zero(C.g, true, x, C.st));
+        S->true_rel_resid = 0.0;
+        return S->status = OK_SUCCESS;
+    }
+    double rr;
+    if (P.zero_guess) {
+        OK_TRY(launch_zero(C.g, true, x, C.st));
+        OK_TRY(launch_copy(C.g, true, r, xi, C.st));
+    } else {
+        OK_TRY(true_residual(C, xi, x, t, r, nullptr, &rr, S));
+    }
+    OK_TRY(cg_start(C, r, p, g, zp));
+    S->matvec_hi++;
+    Scal h;
+    while (true) {
+        if (S->iterations >= P.max_iter) {
+            OK_TRY(true_residual(C, xi, x, t, r, nullptr, &rr, S));
+            S->true_rel_resid = std::sqrt(rr) / xn;
+            return S->status = (S->true_rel_resid <= P.tol) ? OK_SUCCESS : OK_NOT_CONVERGED;
+        }
+        OK_TRY(launch_apply(C.g, C.W64, C.W64_prec, p, w, C.c->mhat, C.tps64, EPI_TS, nullptr, C.w.partial, C.st));
+        OK_TRY(fin(C, FIN_CG_ALPHA, apply_blocks(C.g, C.tps64)));
+        OK_TRY(launch_cg_xr(C.g, x, r, p, w, g, C.w.sc, C.w.partial, C.st));
+        OK_TRY(fin_blas(C, FIN_CG_RR));
+        OK_TRY(launch_apply(C.g, C.W64, C.W64_prec, g, zp, C.c->mhat, C.tps64, EPI_TS, nullptr, C.w.partial, C.st));
+        OK_TRY(fin(C, FIN_CG_BETA, apply_blocks(C.g, C.tps64)));
+        OK_TRY(launch_cg_p(C.g, p, zp, C.w.sc, C.st));
+        S->matvec_hi += 2;
+        S->iterations++;
+        OK_TRY(read_scal(C, &h));
+        const double rel = std::sqrt(h.rr) / xn;
+        if (P.verbose) fprintf(stderr, "okinv cgnr it %d |r|/|xi| %.3e\n", S->iterations, rel);
+        if (!std::isfinite(rel)) {
+            set_error("residual became non-finite at iteration %d", S->iterations);
+            return S->status = OK_ENONFINITE;
+        }
+        const bool broke = h.flags & 1;
+        if (rel <= P.tol || broke) {
+            OK_TRY(true_residual(C, xi, x, t, r, nullptr, &rr, S));
+            S->true_rel_resid = std::sqrt(rr) / xn;
+            if (S->true_rel_resid <= P.tol) return S->status = OK_SUCCESS;
+            if (S->restarts >= P.max_restarts) return S->status = broke ? OK_BREAKDOWN : OK_NOT_CONVERGED;
+            S->restarts++;
+            OK_TRY(cg_start(C, r, p, g, zp));
+            S->matvec_hi++;
+        }
+    }
+}
+
 int solve_mixed(Ctx& C, const double* xi, double* x64, ok_solver_stats* S) {
     const ok_solver_params& P = *C.p;
     double* r64 = C.w.f64[0];
@@ -767,6 +845,87 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
             C.p = &pf;
             rc = solve_mixed(C, d_xi + off, d_psi + off, &S);
         }
+        S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tk).count();
+        if (rc < 0) {
+            S.status = rc;
+            return rc;
+        }
+        if (rc != OK_SUCCESS && first_bad == OK_SUCCESS) first_bad = rc;
+    }
+    return first_bad;
+}
+
+int ok_cgnr_workspace_bytes(const ok_geom* g, int nrhs, size_t* bytes) {
+    Geo G;
+    int rc = make_geo(g, &G);
+    if (rc) return rc;
+    if (nrhs < 1 || !bytes) {
+        set_error("nrhs must be >= 1 and bytes non-NULL");
+        return OK_EINVAL;
+    }
+    *bytes = layout(G, false, 0, nullptr, nullptr);
+    return OK_SUCCESS;
+}
+
+int ok_cgnr(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p, const void* d_W64, const double* d_xi,
+            double* d_psi, int nrhs, void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream) {
+    Ctx C;
+    int rc = make_geo(g, &C.g);
+    if (rc) return rc;
+    if (!c || !p || !stats) {
+        set_error("coefficients, params and stats must be non-NULL");
+        return OK_EINVAL;
+    }
+    if (!std::isfinite(c->mhat) || !(c->u0 > 0)) {
+        set_error("invalid coefficients");
+        return OK_EINVAL;
+    }
+    if (!(p->tol > 0) || p->max_iter < 0 || p->max_restarts < 0) {
+        set_error("invalid solver parameters (tol > 0, max_iter >= 0, max_restarts >= 0)");
+        return OK_EINVAL;
+    }
+    if (p->W64_layout != 0 && p->W64_layout != OK_LAYOUT_SAVED && p->W64_layout != OK_LAYOUT_SIGMA) {
+        set_error("params->W64_layout must be 0, OK_LAYOUT_SAVED or OK_LAYOUT_SIGMA");
+        return OK_EINVAL;
+    }
+    if (nrhs < 1 || nrhs > 4096) {
+        set_error("nrhs = %d outside [1, 4096]", nrhs);
+        return OK_EINVAL;
+    }
+    if ((rc = check_ptr(d_W64, "d_W64")) || (rc = check_ptr(d_xi, "d_xi")) || (rc = check_ptr(d_psi, "d_psi")) ||
+        (rc = check_ptr(d_work, "d_work")))
+        return rc;
+    const size_t need = layout(C.g, false, 0, nullptr, nullptr);
+    if (work_bytes < need) {
+        set_error("workspace has %zu bytes, needs %zu", work_bytes, need);
+        return OK_ESIZE;
+    }
+    const size_t sb = (size_t)C.g.V * 12 * 16 * nrhs;
+    {
+        auto a = reinterpret_cast<uintptr_t>(d_xi), b = reinterpret_cast<uintptr_t>(d_psi);
+        if (a < b + sb && b < a + sb) {
+            set_error("d_psi must not overlap d_xi");
+            return OK_EINVAL;
+        }
+    }
+    layout(C.g, false, 0, reinterpret_cast<char*>(d_work), &C.w);
+    C.c = c;
+    C.p = p;
+    C.W64 = d_W64;
+    C.Wlo = nullptr;
+    C.Wlo_prec = -1;
+    C.net = nullptr;
+    C.st = reinterpret_cast<hipStream_t>(stream);
+    C.W64_prec = OK_F64 | p->W64_layout;
+    C.tps64 = p->W64_layout ? 1 : stencil_tps(OK_F64);
+    C.tpslo = 1;
+    int first_bad = OK_SUCCESS;
+    for (int k = 0; k < nrhs; ++k) {
+        const auto tk = std::chrono::steady_clock::now();
+        ok_solver_stats& S = stats[k];
+        S = ok_solver_stats{};
+        const size_t off = (size_t)k * C.g.V * 24;
+        rc = solve_cgnr(C, d_xi + off, d_psi + off, &S);
         S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tk).count();
         if (rc < 0) {
             S.status = rc;

@@ -81,6 +81,9 @@ _sig = {
     "ok_bicgstab_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.c_int, _NET, C.POINTER(C.c_size_t)], C.c_int),
     "ok_bicgstab": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, C.c_int, _NET,
                      _P, _P, C.c_int, _P, C.c_size_t, C.POINTER(ok_solver_stats), _P], C.c_int),
+    "ok_cgnr_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "ok_cgnr": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, _P, C.c_int, _P,
+                 C.c_size_t, C.POINTER(ok_solver_stats), _P], C.c_int),
     "ok_net_param_count": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "ok_net_transports_bytes": ([C.POINTER(ok_geom), C.POINTER(C.c_size_t)], C.c_int),
     "ok_net_transports": ([C.POINTER(ok_geom), _P, _P, C.c_size_t, _P], C.c_int),
@@ -214,6 +217,22 @@ def ok_bicgstab(dims, c, params, d_W64, d_Wlo, Wlo_prec, d_xi, d_psi, nrhs, d_wo
     rc = _lib.ok_bicgstab(C.byref(geom(dims)), C.byref(coeffs(c)), C.byref(p), _ptr(d_W64), _ptr(d_Wlo),
                           Wlo_prec, _netp(net), _ptr(d_xi), _ptr(d_psi), nrhs, _ptr(d_work), _nbytes(d_work),
                           stats, _stream(stream))
+    _check(rc)
+    return rc, [s.as_dict() for s in stats]
+
+
+def ok_cgnr_workspace_bytes(dims, nrhs):
+    n = C.c_size_t()
+    _check(_lib.ok_cgnr_workspace_bytes(C.byref(geom(dims)), nrhs, C.byref(n)))
+    return n.value
+
+
+def ok_cgnr(dims, c, params, d_W64, d_xi, d_psi, nrhs, d_work, stream=None):
+    """CG on M^dag M (FP64); returns (status, [stats dict per right-hand side])."""
+    stats = (ok_solver_stats * nrhs)()
+    p = params.c() if isinstance(params, SolverParams) else params
+    rc = _lib.ok_cgnr(C.byref(geom(dims)), C.byref(coeffs(c)), C.byref(p), _ptr(d_W64), _ptr(d_xi), _ptr(d_psi),
+                      nrhs, _ptr(d_work), _nbytes(d_work), stats, _stream(stream))
     _check(rc)
     return rc, [s.as_dict() for s in stats]
 

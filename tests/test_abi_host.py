@@ -185,6 +185,26 @@ def test_solver_validation_before_device():
     assert okinv.ok_bicgstab_workspace_bytes(dims, 1, okinv.OK_F32 | okinv.OK_LAYOUT_SIGMA) == need2
 
 
+def test_cgnr_validation_before_device():
+    from paper_1311_5029_amd import okinv
+    dims = (4, 4, 4, 4)
+    c = okinv.coeffs(I.standin_coeffs())
+    g = okinv.geom(dims)
+    lib = okinv._lib
+    stats = (okinv.ok_solver_stats * 1)()
+    need = okinv.ok_cgnr_workspace_bytes(dims, 1)
+    assert need == okinv.ok_bicgstab_workspace_bytes(dims, 1)
+    args = lambda p, work, nrhs=1: (ctypes.byref(g), ctypes.byref(c), ctypes.byref(p), 0x10000000, 0x20000000,
+                                    0x30000000, nrhs, 0x40000000, work, stats, None)
+    good = okinv.SolverParams().c()
+    assert lib.ok_cgnr(*args(good, need - 256)) == okinv.OK_ESIZE
+    assert lib.ok_cgnr(*args(okinv.SolverParams(tol=0.0).c(), need)) == okinv.OK_EINVAL
+    assert lib.ok_cgnr(*args(okinv.SolverParams(W64_layout=okinv.OK_LAYOUT_SITE).c(), need)) == okinv.OK_EINVAL
+    assert lib.ok_cgnr(*args(good, need, 0)) == okinv.OK_EINVAL
+    with pytest.raises(okinv.OkError):
+        okinv.ok_cgnr_workspace_bytes(dims, 0)
+
+
 def test_net_sizes_and_validation_before_device():
     from paper_1311_5029_amd import okinv
     dims = (4, 5, 6, 7)

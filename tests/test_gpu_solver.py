@@ -391,3 +391,58 @@ def test_16x16x16x32_sigma_layout_full_size():
         rc, st, x = solve(L, xi, low=low, w64=SIGMA)
         assert rc == ok.OK_SUCCESS
         assert oracle_resid(cfg["U"], cfg["coeffs"], xi, x) <= ORACLE_SLACK * TOL
+
+
+# --- CG on the normal equations (ok_cgnr) ----------------------------------------------------
+def cgnr(L, xi, w64=0, params=None):
+    ok = L.ok
+    nrhs = xi.shape[0] if xi.ndim == 7 else 1
+    d_xi = ok.to_device_complex(xi)
+    psi = L.torch.zeros_like(d_xi)
+    work = ok.empty_bytes(ok.ok_cgnr_workspace_bytes(L.dims, nrhs))
+    p = params or ok.SolverParams(tol=TOL, max_iter=20000)
+    p.W64_layout = w64
+    rc, st = ok.ok_cgnr(L.dims, L.c, p, L.precompute(ok.OK_F64 | w64), d_xi, psi, nrhs, work)
+    L.torch.cuda.synchronize()
+    return rc, st, ok.to_host_complex(psi, xi.shape)
+
+
+def test_cgnr_4x4x4x4_matches_dense_lu(small):
+    ok = lib()
+    rc, st, x = cgnr(small, small.xi)
+    assert rc == ok.OK_SUCCESS and st[0]["true_rel_resid"] <= TOL
+    assert oracle_resid(small.U, small.c, small.xi, x) <= ORACLE_SLACK * TOL
+    err = np.linalg.norm(x - small.x_lu) / np.linalg.norm(small.x_lu)
+    assert err <= small.kappa * TOL
+    assert st[0]["matvec_hi"] >= 2 * st[0]["iterations"]
+
+
+@pytest.mark.parametrize("w64", [0, SAVED, SIGMA], ids=["dense", "saved", "sigma"])
+def test_cgnr_layouts(mid, w64):
+    """CGNR with the FP64 operator in each layout reaches the oracle's residual bound; the three
+    layouts are the same operator, so the iteration counts agree closely; a zero right-hand side
+    returns zero at once."""
+    ok = lib()
+    L = mid
+    xi = L.xi.copy()
+    xi[1] = 0.0
+    rc, st, x = cgnr(L, xi, w64)
+    assert rc == ok.OK_SUCCESS
+    assert st[1]["iterations"] == 0 and np.all(x[1] == 0)
+    for k in (0, 2):
+        assert oracle_resid(L.U, L.c, xi[k], x[k]) <= ORACLE_SLACK * TOL
+    if not hasattr(L, "cg_its"):
+        L.cg_its = st[0]["iterations"]
+    assert abs(st[0]["iterations"] - L.cg_its) <= 0.05 * L.cg_its + 3
+    rc_b, st_b, _ = solve(L, xi[0])
+    print("CGNR %d iterations (%d applications) vs BiCGStab %d (%d)" % (
+        st[0]["iterations"], st[0]["matvec_hi"], st_b[0]["iterations"], st_b[0]["matvec_hi"]))
+
+
+def test_cgnr_reports_not_converged(small):
+    ok = lib()
+    rc, st, x = cgnr(small, small.xi, params=ok.SolverParams(tol=TOL, max_iter=3))
+    assert rc == ok.OK_NOT_CONVERGED and st[0]["status"] == ok.OK_NOT_CONVERGED
+    assert st[0]["iterations"] == 3 and st[0]["true_rel_resid"] > TOL
+    # the returned iterate is the one whose residual is reported
+    assert abs(oracle_resid(small.U, small.c, small.xi, x) - st[0]["true_rel_resid"]) < 1e-8
