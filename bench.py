@@ -663,11 +663,12 @@ def main():
         # CG on the normal equations (ok_cgnr, sigma-layout FP64 W) on the first two sources, per source,
         # next to BiCGStab with the same operator
         work = ok.empty_bytes(ok.ok_cgnr_workspace_bytes(DIMS, 2))
-        psi = torch.zeros_like(xi[: 2 * V * 24])
+        xi2 = xi.reshape(-1)[: 2 * V * 24]
+        psi = torch.zeros_like(xi2)
         torch.cuda.synchronize()
         t = time.perf_counter()
         rc, st = ok.ok_cgnr(DIMS, c, ok.SolverParams(tol=1e-10, max_iter=20000, W64_layout=SIGMA), Ws[ok.OK_F64 | SIGMA],
-                            xi[: 2 * V * 24], psi, 2, work, stream)
+                            xi2, psi, 2, work, stream)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t
         cg = {"form": "CG on M^dag M (M^dag = gamma5 M gamma5), FP64, sigma-layout W, first 2 of the 12 sources",
