@@ -594,6 +594,11 @@ def main():
             apply_forms["1rhs_" + PREC_NAME[prec] + ("_saved" if lay == SAVED else "_sigma" if lay else "")] = {
                 "ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "rhs_sites_per_s": round(V / (ms * 1e-3), 0)}
+    # 12 right-hand sides with FP32 sigma-layout W (one W read for all of them, no matrix cores)
+    ms = time_apply(ok.OK_F32 | SIGMA, ok.OK_F32 | INNER, NRHS)
+    gbs = (BYTES_SIGMA[1] - 2 * 96 + NRHS * 2 * 96) * V / (ms * 1e-3) / 1e9
+    apply_forms["12rhs_sigma_f32"] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                      "rhs_sites_per_s": round(NRHS * V / (ms * 1e-3), 0)}
     for prec in (ok.OK_F32, ok.OK_BF16):
         ms = time_apply(prec | SITE, ok.OK_F32 | INNER, NRHS)
         gbs = BYTES_STEP[prec] * V / (ms * 1e-3) / 1e9
@@ -635,7 +640,10 @@ def main():
                  ("batched_bf16_sigma64", ok.OK_BF16 | SITE, SIGMA, 3, "as batched_bf16, FP64 reliable updates "
                                                                        "with the sigma-layout FP64 W"),
                  ("mixed_f32_sigma", ok.OK_F32 | SIGMA, SIGMA, 3, "one RHS after the other: FP32 sigma-layout W, "
-                                                                  "FP32 fields, FP64 reliable updates (sigma W)"))
+                                                                  "FP32 fields, FP64 reliable updates (sigma W)"),
+                 ("batched_f32_sigma", ok.OK_F32 | SIGMA | INNER, SIGMA, 3,
+                  "12 RHS together: FP32 sigma-layout W read once for all of them, FP32 fields, FP64 reliable "
+                  "updates (sigma W)"))
         for name, low, w64, reps, desc in forms:
             lp = -1 if low is None else low
             work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(DIMS, NRHS, lp))
@@ -646,7 +654,7 @@ def main():
                 torch.cuda.synchronize()
                 t = time.perf_counter()
                 rc, st = ok.ok_bicgstab(DIMS, c, params, Ws[ok.OK_F64 | w64],
-                                        None if low is None else Ws[low], lp, xi, psi, NRHS, work, stream)
+                                        None if low is None else Ws[low & ~INNER], lp, xi, psi, NRHS, work, stream)
                 torch.cuda.synchronize()
                 secs.append(time.perf_counter() - t)
             sec = float(np.median(secs))

@@ -89,9 +89,10 @@ enum ok_prec { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2 };
 #define OK_LAYOUT_SIGMA 0x200
 
 /* Spinor layout flag OR-ed into spinor_prec of ok_apply_M (FP32 spinors,
- * site-major W, nrhs <= 16): spinors stored [V][4][3][nrhs] complex, the
- * right-hand side index fastest, which the multi-right-hand-side kernel reads
- * contiguously.  Without it spinors are [nrhs][V][4][3]. */
+ * site-major W or FP32 sigma-layout W, nrhs <= 16): spinors stored
+ * [V][4][3][nrhs] complex, the right-hand side index fastest, which the
+ * multi-right-hand-side kernels read contiguously.  Without it spinors are
+ * [nrhs][V][4][3]. */
 #define OK_SPINOR_RHS_INNER 0x20
 
 typedef struct ok_geom {
@@ -192,13 +193,16 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const 
  *           and the final check are FP64).
  *   d_Wlo   NULL: plain FP64 BiCGStab.  Otherwise W at Wlo_prec (OK_F32 or
  *           OK_BF16, optionally | OK_LAYOUT_SAVED, or OK_F32 | OK_LAYOUT_SIGMA,
- *           for one right-hand side at a time; or | OK_LAYOUT_SITE, below):
+ *           for one right-hand side at a time; or | OK_LAYOUT_SITE, or
+ *           OK_F32 | OK_LAYOUT_SIGMA | OK_SPINOR_RHS_INNER, below):
  *           the iteration runs in FP32 fields with that operator and
  *           FP64 reliable updates (x accumulated and r recomputed in FP64 when
  *           the low-precision residual drops by params->delta).  With
- *           Wlo_prec | OK_LAYOUT_SITE the right-hand sides (in groups of up to
- *           16) iterate together: one matrix-core application of W per
- *           BiCGStab step for the whole group, per-right-hand-side scalars,
+ *           Wlo_prec | OK_LAYOUT_SITE (or FP32 sigma-layout W with
+ *           OK_SPINOR_RHS_INNER) the right-hand sides (in groups of up to
+ *           16) iterate together: one application of W per BiCGStab step for
+ *           the whole group (on the matrix cores for site-major W; the sigma
+ *           layout reads each matrix once for all of them), per-right-hand-side scalars,
  *           reliable updates and convergence.  When a right-hand side is due
  *           for a reliable update, every one whose residual has fallen below
  *           sqrt(delta) of its maximum is updated in the same FP64 pass (W64

@@ -204,8 +204,9 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
     const bool site_major = (W_prec & OK_LAYOUT_SITE) != 0;
     const bool saved = (W_prec & (OK_LAYOUT_SAVED | OK_LAYOUT_SIGMA)) != 0;   // one thread per site
     const bool rhs_inner = (spinor_prec & OK_SPINOR_RHS_INNER) != 0;
-    if (rhs_inner && (!site_major || nrhs > 16)) {
-        set_error("OK_SPINOR_RHS_INNER needs site-major W (OK_LAYOUT_SITE) and nrhs <= 16");
+    const bool sigma32 = (W_prec & OK_LAYOUT_SIGMA) && wbase == OK_F32;
+    if (rhs_inner && (!(site_major || sigma32) || nrhs > 16)) {
+        set_error("OK_SPINOR_RHS_INNER needs site-major W (OK_LAYOUT_SITE) or FP32 sigma-layout W, and nrhs <= 16");
         return OK_EINVAL;
     }
     spinor_prec &= ~OK_SPINOR_RHS_INNER;
@@ -228,6 +229,9 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
         return OK_EINVAL;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (rhs_inner && sigma32)
+        return launch_apply_sigma_mr(G, d_W, reinterpret_cast<const float*>(d_psi), reinterpret_cast<float*>(d_out),
+                                     c->mhat, nrhs, st);
     if (site_major)
         return launch_apply_site(G, d_W, wbase, reinterpret_cast<const float*>(d_psi),
                                  reinterpret_cast<float*>(d_out), c->mhat, nrhs, rhs_inner ? 1 : 0, st);

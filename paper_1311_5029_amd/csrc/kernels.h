@@ -56,6 +56,9 @@ int stencil_tps(int Wprec);
 int apply_blocks(const Geo& g, int tps);
 int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int tps,
                  int epi, const void* aux, double2* partial, hipStream_t st);
+// FP32 sigma-layout W on nrhs (<= 16) right-hand sides stored [V][12][nrhs] (no epilogue)
+int launch_apply_sigma_mr(const Geo& g, const void* W, const float* psi, float* out, double mhat, int nrhs,
+                          hipStream_t st);
 // W in OK_LAYOUT_SIGMA (FP64 or FP32), one thread per site (stencil_sigma.hip)
 int launch_apply_sigma(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int epi,
                        const void* aux, double2* partial, hipStream_t st);

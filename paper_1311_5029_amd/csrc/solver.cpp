@@ -451,6 +451,12 @@ int write_active(Ctx& C, WorkB& B, const ScalB* h) {
     return OK_SUCCESS;
 }
 
+// The low-precision operator on nrhs right-hand-side-inner FP32 fields of the batched solve.
+int apply_lo_batched(Ctx& C, const float* in, float* out, int nrhs) {
+    if (C.Wlo_prec & OK_LAYOUT_SIGMA) return launch_apply_sigma_mr(C.g, C.Wlo, in, out, C.c->mhat, nrhs, C.st);
+    return launch_apply_site(C.g, C.Wlo, C.Wlo_prec & ~OK_LAYOUT_SITE, in, out, C.c->mhat, nrhs, 1, C.st);
+}
+
 // For every column j in cols[0..n): x64_j += x32[:, j]; r[:, j] = xi_j - M64 x64_j;
 // rr[j] = ||r_j||^2 in FP64.  xi and x are the bases of the [nrhs][V][12] FP64 fields.
 // The FP64 operator runs on up to four columns per pass, reading W once per pass.
@@ -559,7 +565,6 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
         return false;
     };
     int it = 0;
-    const int wp = C.Wlo_prec & ~OK_LAYOUT_SITE;
     while (any_active()) {
         if (it >= P.max_iter) {
             int cols[kMaxRhsB], n = 0;
@@ -581,12 +586,12 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
         float* sh = C.net ? B.f[8] : s;
         OK_TRY(launch_bp_update(g, nrhs, p, r, v, B.sc, C.st));
         if (C.net) OK_TRY(apply_net(C, p, ph, nrhs, true, B.netw));
-        OK_TRY(launch_apply_site(g, C.Wlo, wp, ph, v, C.c->mhat, nrhs, 1, C.st));
+        OK_TRY(apply_lo_batched(C, ph, v, nrhs));
         OK_TRY(launch_bdot(g, nrhs, rhat, v, B.sc, B.partial, C.st));
         OK_TRY(bfin(C, B, FIN_ALPHA, kGridB, 0, nrhs));
         OK_TRY(launch_bs_update(g, nrhs, s, r, v, B.sc, C.st));
         if (C.net) OK_TRY(apply_net(C, s, sh, nrhs, true, B.netw));
-        OK_TRY(launch_apply_site(g, C.Wlo, wp, sh, t, C.c->mhat, nrhs, 1, C.st));
+        OK_TRY(apply_lo_batched(C, sh, t, nrhs));
         OK_TRY(launch_bdot(g, nrhs, t, s, B.sc, B.partial, C.st));
         OK_TRY(bfin(C, B, FIN_OMEGA, kGridB, 0, nrhs));
         OK_TRY(launch_bxr_update(g, nrhs, x32, r, ph, sh, s, t, rhat, B.sc, B.partial, C.st));
@@ -683,8 +688,16 @@ extern "C" {
 
 namespace {
 
-// low-precision operator of a mixed solve: F32 / BF16, at most one layout flag, sigma only in F32
+// the right-hand sides iterate together: site-major W on the matrix cores, or FP32 sigma-layout W
+// with right-hand-side-inner fields
+bool is_batched(int wlo) {
+    return wlo >= 0 && ((wlo & OK_LAYOUT_SITE) || ((wlo & OK_LAYOUT_SIGMA) && (wlo & OK_SPINOR_RHS_INNER)));
+}
+
+// low-precision operator of a mixed solve: F32 / BF16, at most one layout flag, sigma only in F32;
+// F32 | OK_LAYOUT_SIGMA | OK_SPINOR_RHS_INNER selects the batched solve with the sigma layout
 bool valid_wlo(int p) {
+    if (p & OK_SPINOR_RHS_INNER) return (p & ~OK_SPINOR_RHS_INNER) == (OK_F32 | OK_LAYOUT_SIGMA);
     const int lay = p & (OK_LAYOUT_SITE | OK_LAYOUT_SAVED | OK_LAYOUT_SIGMA), b = p & ~lay;
     if (lay & (lay - 1)) return false;
     if (lay == OK_LAYOUT_SIGMA) return b == OK_F32;
@@ -707,7 +720,7 @@ int check_solver_net(const ok_net* net, bool mixed) {
 
 size_t workspace(const Geo& G, int nrhs, int Wlo_prec, const ok_net* net) {
     const int nl = net ? net->n_layers : 0;
-    if (Wlo_prec >= 0 && (Wlo_prec & OK_LAYOUT_SITE)) return layout_batched(G, std::min(nrhs, kMaxRhsB), nl, nullptr, nullptr);
+    if (is_batched(Wlo_prec)) return layout_batched(G, std::min(nrhs, kMaxRhsB), nl, nullptr, nullptr);
     return layout(G, Wlo_prec >= 0, nl, nullptr, nullptr);
 }
 
@@ -723,7 +736,7 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const 
     }
     if (Wlo_prec >= 0 && !valid_wlo(Wlo_prec)) {
         set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE or OK_LAYOUT_SAVED), "
-                  "OK_F32 | OK_LAYOUT_SIGMA, or negative (plain FP64)");
+                  "OK_F32 | OK_LAYOUT_SIGMA (optionally | OK_SPINOR_RHS_INNER), or negative (plain FP64)");
         return OK_EINVAL;
     }
     if ((rc = check_solver_net(net, Wlo_prec >= 0))) return rc;
@@ -758,7 +771,7 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
     const int wlb = Wlo_prec & 3;
     if (mixed && !valid_wlo(Wlo_prec)) {
         set_error("Wlo_prec must be OK_F32 or OK_BF16 (optionally | OK_LAYOUT_SITE or OK_LAYOUT_SAVED), or "
-                  "OK_F32 | OK_LAYOUT_SIGMA, when d_Wlo is given");
+                  "OK_F32 | OK_LAYOUT_SIGMA (optionally | OK_SPINOR_RHS_INNER), when d_Wlo is given");
         return OK_EINVAL;
     }
     if (p->W64_layout != 0 && p->W64_layout != OK_LAYOUT_SAVED && p->W64_layout != OK_LAYOUT_SIGMA) {
@@ -766,7 +779,7 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
         return OK_EINVAL;
     }
     if ((rc = check_solver_net(net, mixed))) return rc;
-    const bool batched = mixed && (Wlo_prec & OK_LAYOUT_SITE);
+    const bool batched = mixed && is_batched(Wlo_prec);
     if ((rc = check_ptr(d_W64, "d_W64")) || (mixed && (rc = check_ptr(d_Wlo, "d_Wlo"))) ||
         (rc = check_ptr(d_xi, "d_xi")) || (rc = check_ptr(d_psi, "d_psi")) || (rc = check_ptr(d_work, "d_work")))
         return rc;

@@ -240,31 +240,46 @@ __device__ __forceinline__ void hop_w0(const void* __restrict__ W, int Vs, int s
     }
 }
 
+// spinor component q of site s: [V][12] (nr = 0), or right-hand side r of [V][12][nr] (nr > 0)
 template <typename T>
-__device__ __forceinline__ void ld_sp(const T* __restrict__ psi, int s, cpx<T> v[12]) {
-    const cpx<T>* p = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12;
+__device__ __forceinline__ void ld_sp(const T* __restrict__ psi, int s, cpx<T> v[12], int nr = 0, int r = 0) {
+    const cpx<T>* p = reinterpret_cast<const cpx<T>*>(psi);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) v[q] = p[q];
+    for (int q = 0; q < 12; ++q) v[q] = nr ? p[((size_t)s * 12 + q) * nr + r] : p[(size_t)s * 12 + q];
 }
 
-template <int P, int EPI>
+// MR = 0: one thread per site, spinors [V][12].  MR = 1: nr (<= 16) right-hand sides with the
+// right-hand side fastest ([V][12][nr]); lane l of a wavefront takes site slot l / nr and
+// right-hand side l % nr (64 / nr sites per wavefront), so the lanes of a site issue the same
+// matrix addresses and each W byte is fetched once for all right-hand sides.
+template <int P, int EPI, int MR>
 __global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restrict__ W,
                                                      const typename SArith<P>::T* __restrict__ psi,
                                                      typename SArith<P>::T* __restrict__ out, double mhat_d,
                                                      const typename SArith<P>::T* __restrict__ aux,
-                                                     double2* __restrict__ partial) {
+                                                     double2* __restrict__ partial, int nr) {
     using T = typename SArith<P>::T;
     // each XCD takes a contiguous range of sites, so that the matrices a site's neighbours
     // read again as their backward blocks are still in that XCD's L2
-    const int s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const bool live = s < g.V;
+    int s, r = 0;
+    bool live;
+    if constexpr (MR) {
+        const int lane = threadIdx.x & 63, spw = 64 / nr, slot = lane / nr;
+        r = lane - slot * nr;
+        s = (xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * spw + slot;
+        live = slot < spw && s < g.V;
+    } else {
+        nr = 0;
+        s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+        live = s < g.V;
+    }
     double2 d1{0.0, 0.0}, d2{0.0, 0.0};
     if (live) {
         const int Vs = g.Vs;
         int x, y, z, t;
         site_coords(g, s, x, y, z, t);
         cpx<T> acc[2][2][3], v[12];
-        ld_sp(psi, s, v);
+        ld_sp(psi, s, v, nr, r);
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -275,27 +290,27 @@ __global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restri
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {   // +-i: W+_i at x, Gamma(W+_i) at x - i
             int n = neighbour(g, x, y, z, t, off_d(1 + i, 0), off_d(1 + i, 1), off_d(1 + i, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_ds<P, false, T>(W, Vs, s, SG_WI + 8 * i, v, acc);
             n = neighbour(g, x, y, z, t, -off_d(1 + i, 0), -off_d(1 + i, 1), -off_d(1 + i, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_ds<P, true, T>(W, Vs, n, SG_WI + 8 * i, v, acc);
         }
         {   // +-t
             int n = neighbour(g, x, y, z, t, 0, 0, 0, 1);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_t<P, false, T>(W, Vs, s, SG_W4, v, acc);
             n = neighbour(g, x, y, z, t, 0, 0, 0, -1);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_t<P, true, T>(W, Vs, n, SG_W4, v, acc);
         }
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {   // +-2i
             int n = neighbour(g, x, y, z, t, off_d(9 + i, 0), off_d(9 + i, 1), off_d(9 + i, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_ii<P, false, T>(W, Vs, s, SG_WII + 2 * i, i, v, acc);
             n = neighbour(g, x, y, z, t, -off_d(9 + i, 0), -off_d(9 + i, 1), -off_d(9 + i, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_ii<P, true, T>(W, Vs, n, SG_WII + 2 * i, i, v, acc);
         }
 #pragma unroll 1
@@ -303,21 +318,22 @@ __global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restri
             const int i = p < 2 ? 0 : 1, j = p == 0 ? 1 : 2;
             const int k1 = 15 + p, k2 = 21 + p;
             int n = neighbour(g, x, y, z, t, off_d(k1, 0), off_d(k1, 1), off_d(k1, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_off<P, false, T>(W, Vs, s, SG_WIJ + p, i, j, T(1), v, acc);
             n = neighbour(g, x, y, z, t, -off_d(k1, 0), -off_d(k1, 1), -off_d(k1, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_off<P, true, T>(W, Vs, n, SG_WIJ + p, i, j, T(1), v, acc);
             n = neighbour(g, x, y, z, t, off_d(k2, 0), off_d(k2, 1), off_d(k2, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_off<P, false, T>(W, Vs, s, SG_WIMJ + p, i, j, T(-1), v, acc);
             n = neighbour(g, x, y, z, t, -off_d(k2, 0), -off_d(k2, 1), -off_d(k2, 2), 0);
-            ld_sp(psi, n, v);
+            ld_sp(psi, n, v, nr, r);
             hop_off<P, true, T>(W, Vs, n, SG_WIMJ + p, i, j, T(-1), v, acc);
         }
-        cpx<T>* o = reinterpret_cast<cpx<T>*>(out) + (size_t)s * 12;
+        cpx<T>* o = reinterpret_cast<cpx<T>*>(out);
 #pragma unroll
-        for (int q = 0; q < 12; ++q) o[q] = acc[q / 6][(q / 3) & 1][q % 3];
+        for (int q = 0; q < 12; ++q)
+            o[MR ? ((size_t)s * 12 + q) * nr + r : (size_t)s * 12 + q] = acc[q / 6][(q / 3) & 1][q % 3];
         if constexpr (EPI == EPI_RV) {
             const cpx<T>* a = reinterpret_cast<const cpx<T>*>(aux) + (size_t)s * 12;
 #pragma unroll
@@ -348,14 +364,28 @@ int launch_sigma_t(const Geo& g, const void* W, const void* psi, void* out, doub
     const T* in = reinterpret_cast<const T*>(psi);
     T* o = reinterpret_cast<T*>(out);
     const T* ax = reinterpret_cast<const T*>(aux);
-    if (epi == EPI_NONE) k_apply_sigma<P, EPI_NONE><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
-    else if (epi == EPI_RV) k_apply_sigma<P, EPI_RV><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
-    else k_apply_sigma<P, EPI_TS><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial);
+    if (epi == EPI_NONE) k_apply_sigma<P, EPI_NONE, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0);
+    else if (epi == EPI_RV) k_apply_sigma<P, EPI_RV, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0);
+    else k_apply_sigma<P, EPI_TS, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0);
     OK_LAUNCH_CHECK("k_apply_sigma");
     return OK_SUCCESS;
 }
 
 }  // namespace
+
+int launch_apply_sigma_mr(const Geo& g, const void* W, const float* psi, float* out, double mhat, int nrhs,
+                          hipStream_t st) {
+    if (nrhs < 1 || nrhs > 16) {
+        set_error("right-hand-side-inner spinors support 1 to 16 right-hand sides");
+        return OK_EINVAL;
+    }
+    const int spw = 64 / nrhs;
+    const long waves = ((long)g.V + spw - 1) / spw;
+    const unsigned nb = (unsigned)((waves + 3) / 4);
+    k_apply_sigma<OK_F32, EPI_NONE, 1><<<nb, 256, 0, st>>>(g, W, psi, out, mhat, nullptr, nullptr, nrhs);
+    OK_LAUNCH_CHECK("k_apply_sigma");
+    return OK_SUCCESS;
+}
 
 int launch_apply_sigma(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int epi,
                        const void* aux, double2* partial, hipStream_t st) {

@@ -183,6 +183,14 @@ def test_solver_validation_before_device():
         with pytest.raises(okinv.OkError):
             okinv.ok_bicgstab_workspace_bytes(dims, 1, wlo)
     assert okinv.ok_bicgstab_workspace_bytes(dims, 1, okinv.OK_F32 | okinv.OK_LAYOUT_SIGMA) == need2
+    # the batched solve: site-major W, or FP32 sigma W with right-hand-side-inner fields
+    inner = okinv.OK_SPINOR_RHS_INNER
+    assert (okinv.ok_bicgstab_workspace_bytes(dims, 4, okinv.OK_F32 | okinv.OK_LAYOUT_SIGMA | inner) ==
+            okinv.ok_bicgstab_workspace_bytes(dims, 4, okinv.OK_F32 | okinv.OK_LAYOUT_SITE))
+    for wlo in (okinv.OK_F32 | inner, okinv.OK_BF16 | okinv.OK_LAYOUT_SIGMA | inner,
+                okinv.OK_F32 | okinv.OK_LAYOUT_SITE | inner):
+        with pytest.raises(okinv.OkError):
+            okinv.ok_bicgstab_workspace_bytes(dims, 4, wlo)
 
 
 def test_cgnr_validation_before_device():

@@ -33,7 +33,7 @@ def solve(L, xi, low=None, params=None, guess=None, net=None, w64=0):
     lo_prec = -1 if low is None else low
     work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(L.dims, nrhs, lo_prec, net))
     W64 = L.precompute(ok.OK_F64 | w64)
-    Wlo = None if low is None else L.precompute(low)
+    Wlo = None if low is None else L.precompute(low & ~0x20)   # the spinor flag is not part of W's layout
     p = params or ok.SolverParams(tol=TOL)
     p.W64_layout = w64
     if guess is not None:
@@ -268,12 +268,12 @@ def test_trained_network_cuts_iterations(learned_small):
         assert oracle_resid(L.U, L.c, xi, x1) <= ORACLE_SLACK * TOL
 
 
-@pytest.mark.parametrize("low", [1, 2], ids=["f32", "bf16"])
+@pytest.mark.parametrize("low", [1 | SITE, 2 | SITE, 1 | 0x200 | 0x20], ids=["f32", "bf16", "f32-sigma"])
 def test_batched_with_network(learned_small, low):
     ok = lib()
     L = learned_small
-    rc0, st0, _ = solve(L, L.xi_eval, low=low | SITE)
-    rc1, st1, x = solve(L, L.xi_eval, low=low | SITE, net=L.net)
+    rc0, st0, _ = solve(L, L.xi_eval, low=low)
+    rc1, st1, x = solve(L, L.xi_eval, low=low, net=L.net)
     assert rc0 == rc1 == ok.OK_SUCCESS
     for k in range(4):
         assert st1[k]["fallbacks"] == 0
@@ -361,16 +361,17 @@ def mid():
 
 
 @pytest.mark.parametrize("w64,low", [(SIGMA, None), (SAVED, None), (SIGMA, 1 | SIGMA), (SAVED, 2 | SAVED),
-                                     (SIGMA, 1), (SIGMA, 2 | 0x10)],
-                         ids=["plain-sigma", "plain-saved", "f32-sigma", "bf16-saved", "f32-dense-lo", "batched-bf16"])
+                                     (SIGMA, 1), (SIGMA, 2 | 0x10), (SIGMA, 1 | SIGMA | 0x20)],
+                         ids=["plain-sigma", "plain-saved", "f32-sigma", "bf16-saved", "f32-dense-lo", "batched-bf16",
+                              "batched-f32-sigma"])
 def test_compact_layouts_in_solver(mid, w64, low):
     """Plain, mixed and batched solves with the FP64 (and low-precision) operator in the saved or
     sigma layout reach the oracle's residual bound in about as many iterations as with 27 dense
     blocks (the same operator up to rounding)."""
     ok = lib()
     L = mid
-    dense_low = None if low is None else low & ~(SAVED | SIGMA)
-    xi = L.xi if (low or 0) & 0x10 else L.xi[0]
+    dense_low = None if low is None else 1 | 0x10 if low & 0x20 else low & ~(SAVED | SIGMA)
+    xi = L.xi if (low or 0) & 0x30 else L.xi[0]
     rc0, st0, _ = solve(L, xi, low=dense_low)
     rc1, st1, x = solve(L, xi, low=low, w64=w64)
     assert rc0 == rc1 == ok.OK_SUCCESS
