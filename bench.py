@@ -40,6 +40,8 @@ BYTES_SITE = {0: 27 * 144 * 16 + 2 * 192, 1: 27 * 144 * 8 + 2 * 96, 2: 27 * 144 
 BYTES_SAVED = {0: 14 * 144 * 16 + 2 * 192, 1: 14 * 144 * 8 + 2 * 96, 2: 14 * 144 * 4 + 2 * 96}
 # W as 46 Pauli-component colour matrices per site (OK_LAYOUT_SIGMA), each read once from HBM
 BYTES_SIGMA = {0: 46 * 9 * 16 + 2 * 192, 1: 46 * 9 * 8 + 2 * 96}
+# ... and the sigma layout on the 12-RHS batch (FP32): W once + 12 spinors in and out
+BYTES_SIGMA_MR = {1: 46 * 9 * 8 + NRHS * 2 * 96}
 # ... and of one application to the 12-RHS batch by the MFMA kernel: W streamed
 # once for all right-hand sides + 12 spinors in and out (FP64 W: 12 single launches)
 BYTES_STEP = {0: NRHS * BYTES_SITE[0], 1: 27 * 144 * 8 + NRHS * 2 * 96, 2: 27 * 144 * 4 + NRHS * 2 * 96}
@@ -54,7 +56,8 @@ def log(msg):
 def source_hash(kernel="k_apply"):
     """Hash of the sources of a kernel (its file plus the shared layout headers)."""
     h = hashlib.sha256()
-    main = {"k_apply": "stencil.hip", "k_apply_sigma": "stencil_sigma.hip"}.get(kernel, "stencil_mrhs.hip")
+    main = {"k_apply": "stencil.hip", "k_apply_sigma": "stencil_sigma.hip",
+            "k_apply_sigma_mr": "stencil_sigma.hip"}.get(kernel, "stencil_mrhs.hip")
     for f in (main, "wlayout.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1311_5029_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -91,8 +94,11 @@ def is_apply_kernel(name, form, kernel="k_apply"):
         return ("k_apply_site<%d, 1>" % p) in name or ("k_apply_siteILi%dELi1E" % p) in name
     if kernel == "k_apply_mrhs":
         return ("k_apply_mrhs<%d>" % p) in name or ("k_apply_mrhsILi%dE" % p) in name
-    if kernel in ("k_apply_saved", "k_apply_sigma"):   # <prec, no epilogue>
-        return ("%s<%d, 0>" % (kernel, p)) in name or ("%sILi%dELi0E" % (kernel, p)) in name
+    if kernel == "k_apply_saved":   # <prec, no epilogue>
+        return ("k_apply_saved<%d, 0>" % p) in name or ("k_apply_savedILi%dELi0E" % p) in name
+    if kernel in ("k_apply_sigma", "k_apply_sigma_mr"):   # <prec, no epilogue, right-hand-side-inner>
+        mr = 1 if kernel == "k_apply_sigma_mr" else 0
+        return ("k_apply_sigma<%d, 0, %d>" % (p, mr)) in name or ("k_apply_sigmaILi%dELi0ELi%dE" % (p, mr)) in name
     return any(("k_apply<%d, %d, 0>" % (p, t)) in name or ("k_applyILi%dELi%dELi0E" % (p, t)) in name
                for t in (1, 2, 4))
 
@@ -131,9 +137,10 @@ def parse_pmc(fetch_dir, write_dir, form):
     summary per kernel found (consumed by the benchmark's roofline entry)."""
     prec = {"f64": 0, "f32": 1, "bf16": 2}[form]
     algo = {"k_apply": BYTES_SITE[prec] * V, "k_apply_mrhs": BYTES_STEP[prec] * V,
-            "k_apply_site": BYTES_STEP[prec] * V, "k_apply_sigma": BYTES_SIGMA.get(prec, 0) * V}
+            "k_apply_site": BYTES_STEP[prec] * V, "k_apply_sigma": BYTES_SIGMA.get(prec, 0) * V,
+            "k_apply_sigma_mr": BYTES_SIGMA_MR.get(prec, 0) * V}
     rows = {c: _read_counters(d) for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))}
-    for kernel in ("k_apply", "k_apply_mrhs", "k_apply_site", "k_apply_sigma"):
+    for kernel in ("k_apply", "k_apply_mrhs", "k_apply_site", "k_apply_sigma", "k_apply_sigma_mr"):
         res = {}
         for cname in ("FETCH_SIZE", "WRITE_SIZE"):
             ker = [v[cname] for (k, _), v in rows[cname].items() if cname in v and is_apply_kernel(k, form, kernel)]
@@ -171,7 +178,7 @@ def summarize_trace(d, out_path, command):
         name = re.sub(r"\(.*", "", name).replace("void ", "")[:44]
         lines.append("%-44s %6s %14.0f %8.2f" % (name, r["Calls"], float(r["AverageNs"]), float(r["Percentage"])))
     for kernel, per_site in (("k_apply", BYTES_SITE), ("k_apply_site", BYTES_STEP), ("k_apply_saved", BYTES_SAVED),
-                             ("k_apply_sigma", BYTES_SIGMA)):
+                             ("k_apply_sigma", BYTES_SIGMA), ("k_apply_sigma_mr", BYTES_SIGMA_MR)):
         for form, prec in (("f64", 0), ("f32", 1), ("bf16", 2)):
             if prec not in per_site:
                 continue
@@ -182,7 +189,8 @@ def summarize_trace(d, out_path, command):
                     lines.append("")
                     lines.append("%s<%s> (%s): average %.0f ns per launch -> %.1f GB/s algorithmic "
                                  "(%d B/site x %d sites), %.1f%% of 8 TB/s"
-                                 % (kernel, form, "12 RHS" if kernel == "k_apply_site" else "1 RHS", ns, gbs,
+                                 % (kernel, form, "12 RHS" if kernel in ("k_apply_site", "k_apply_sigma_mr")
+                                    else "1 RHS", ns, gbs,
                                     per_site[prec], V, gbs / HBM_PEAK_GBS * 100))
                     break
     with open(out_path, "w") as fh:
