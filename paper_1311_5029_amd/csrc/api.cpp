@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -238,6 +239,15 @@ int ok_apply_M(const ok_geom* g, const ok_coeffs* c, const void* d_W, int W_prec
     if (nrhs > 1 && wbase != OK_F64 && !saved && use_mrhs())
         return launch_apply_mrhs(G, d_W, W_prec, reinterpret_cast<const float*>(d_psi),
                                  reinterpret_cast<float*>(d_out), c->mhat, nrhs, st);
+    if ((W_prec & OK_LAYOUT_SIGMA) && wbase == OK_F64 && nrhs > 1) {   // W read once per four right-hand sides
+        std::vector<const double*> in(nrhs);
+        std::vector<double*> out(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            in[r] = reinterpret_cast<const double*>(reinterpret_cast<const char*>(d_psi) + sb * r);
+            out[r] = reinterpret_cast<double*>(reinterpret_cast<char*>(d_out) + sb * r);
+        }
+        return launch_apply_sigma_cols(G, d_W, in.data(), out.data(), nrhs, c->mhat, st);
+    }
     const int tps = saved ? 1 : stencil_tps(W_prec);
     for (int r = 0; r < nrhs; ++r) {
         const char* in = reinterpret_cast<const char*>(d_psi) + sb * r;

@@ -59,6 +59,9 @@ int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* 
 // FP32 sigma-layout W on nrhs (<= 16) right-hand sides stored [V][12][nrhs] (no epilogue)
 int launch_apply_sigma_mr(const Geo& g, const void* W, const float* psi, float* out, double mhat, int nrhs,
                           hipStream_t st);
+// FP64 sigma-layout W on n separate [V][12] fields, up to four per pass (W read once per pass)
+int launch_apply_sigma_cols(const Geo& g, const void* W, const double* const* in, double* const* out, int n,
+                            double mhat, hipStream_t st);
 // W in OK_LAYOUT_SIGMA (FP64 or FP32), one thread per site (stencil_sigma.hip)
 int launch_apply_sigma(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int epi,
                        const void* aux, double2* partial, hipStream_t st);

@@ -475,7 +475,9 @@ int batched_true_residuals(Ctx& C, WorkB& B, int nrhs, const int* cols, int n, c
         }
         if (C.W64_prec == OK_F64) {
             OK_TRY(launch_apply_m64(g, C.W64, in, out, m, C.c->mhat, C.st));
-        } else {   // saved or sigma layout: one single-right-hand-side application per column
+        } else if (C.W64_prec & OK_LAYOUT_SIGMA) {
+            OK_TRY(launch_apply_sigma_cols(g, C.W64, in, out, m, C.c->mhat, C.st));
+        } else {   // saved layout: one single-right-hand-side application per column
             for (int r = 0; r < m; ++r)
                 OK_TRY(launch_apply(g, C.W64, C.W64_prec, in[r], out[r], C.c->mhat, 1, EPI_NONE, nullptr, nullptr,
                                     C.st));

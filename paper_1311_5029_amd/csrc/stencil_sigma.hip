@@ -18,6 +18,8 @@
 // read at the site and again as the backward blocks of its neighbours, one spinor out, and
 // 27 neighbour spinors (L2 hits mostly); 232 colour matrix-vector products (2,088 complex
 // multiply-adds, against 3,888 for 27 dense blocks).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "wlayout.h"
@@ -248,16 +250,25 @@ __device__ __forceinline__ void ld_sp(const T* __restrict__ psi, int s, cpx<T> v
     for (int q = 0; q < 12; ++q) v[q] = nr ? p[((size_t)s * 12 + q) * nr + r] : p[(size_t)s * 12 + q];
 }
 
+// Up to four separate [V][12] fields (MR == 2).
+template <typename T>
+struct SCols {
+    const T* in[4];
+    T* out[4];
+};
+
 // MR = 0: one thread per site, spinors [V][12].  MR = 1: nr (<= 16) right-hand sides with the
-// right-hand side fastest ([V][12][nr]); lane l of a wavefront takes site slot l / nr and
-// right-hand side l % nr (64 / nr sites per wavefront), so the lanes of a site issue the same
-// matrix addresses and each W byte is fetched once for all right-hand sides.
+// right-hand side fastest ([V][12][nr]); MR = 2: nr (<= 4) separate [V][12] fields in cols.
+// With MR > 0 lane l of a wavefront takes site slot l / nr and right-hand side l % nr (64 / nr
+// sites per wavefront), so the lanes of a site issue the same matrix addresses and each W byte is
+// fetched once for all right-hand sides.
 template <int P, int EPI, int MR>
 __global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restrict__ W,
                                                      const typename SArith<P>::T* __restrict__ psi,
                                                      typename SArith<P>::T* __restrict__ out, double mhat_d,
                                                      const typename SArith<P>::T* __restrict__ aux,
-                                                     double2* __restrict__ partial, int nr) {
+                                                     double2* __restrict__ partial, int nr,
+                                                     SCols<typename SArith<P>::T> cols) {
     using T = typename SArith<P>::T;
     // each XCD takes a contiguous range of sites, so that the matrices a site's neighbours
     // read again as their backward blocks are still in that XCD's L2
@@ -268,6 +279,12 @@ __global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restri
         r = lane - slot * nr;
         s = (xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * spw + slot;
         live = slot < spw && s < g.V;
+        if constexpr (MR == 2) {   // this lane's field, addressed as one [V][12] spinor
+            psi = r == 0 ? cols.in[0] : r == 1 ? cols.in[1] : r == 2 ? cols.in[2] : cols.in[3];
+            out = r == 0 ? cols.out[0] : r == 1 ? cols.out[1] : r == 2 ? cols.out[2] : cols.out[3];
+            nr = 0;
+            r = 0;
+        }
     } else {
         nr = 0;
         s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -333,7 +350,7 @@ __global__ void __launch_bounds__(256) k_apply_sigma(Geo g, const void* __restri
         cpx<T>* o = reinterpret_cast<cpx<T>*>(out);
 #pragma unroll
         for (int q = 0; q < 12; ++q)
-            o[MR ? ((size_t)s * 12 + q) * nr + r : (size_t)s * 12 + q] = acc[q / 6][(q / 3) & 1][q % 3];
+            o[MR == 1 ? ((size_t)s * 12 + q) * nr + r : (size_t)s * 12 + q] = acc[q / 6][(q / 3) & 1][q % 3];
         if constexpr (EPI == EPI_RV) {
             const cpx<T>* a = reinterpret_cast<const cpx<T>*>(aux) + (size_t)s * 12;
 #pragma unroll
@@ -364,9 +381,10 @@ int launch_sigma_t(const Geo& g, const void* W, const void* psi, void* out, doub
     const T* in = reinterpret_cast<const T*>(psi);
     T* o = reinterpret_cast<T*>(out);
     const T* ax = reinterpret_cast<const T*>(aux);
-    if (epi == EPI_NONE) k_apply_sigma<P, EPI_NONE, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0);
-    else if (epi == EPI_RV) k_apply_sigma<P, EPI_RV, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0);
-    else k_apply_sigma<P, EPI_TS, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0);
+    const SCols<T> nc{};
+    if (epi == EPI_NONE) k_apply_sigma<P, EPI_NONE, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0, nc);
+    else if (epi == EPI_RV) k_apply_sigma<P, EPI_RV, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0, nc);
+    else k_apply_sigma<P, EPI_TS, 0><<<nb, 256, 0, st>>>(g, W, in, o, mhat, ax, partial, 0, nc);
     OK_LAUNCH_CHECK("k_apply_sigma");
     return OK_SUCCESS;
 }
@@ -382,8 +400,28 @@ int launch_apply_sigma_mr(const Geo& g, const void* W, const float* psi, float* 
     const int spw = 64 / nrhs;
     const long waves = ((long)g.V + spw - 1) / spw;
     const unsigned nb = (unsigned)((waves + 3) / 4);
-    k_apply_sigma<OK_F32, EPI_NONE, 1><<<nb, 256, 0, st>>>(g, W, psi, out, mhat, nullptr, nullptr, nrhs);
+    k_apply_sigma<OK_F32, EPI_NONE, 1><<<nb, 256, 0, st>>>(g, W, psi, out, mhat, nullptr, nullptr, nrhs,
+                                                           SCols<float>{});
     OK_LAUNCH_CHECK("k_apply_sigma");
+    return OK_SUCCESS;
+}
+
+int launch_apply_sigma_cols(const Geo& g, const void* W, const double* const* in, double* const* out, int n,
+                            double mhat, hipStream_t st) {
+    for (int c0 = 0; c0 < n; c0 += 4) {
+        const int m = std::min(4, n - c0);
+        SCols<double> cols{};
+        for (int c = 0; c < m; ++c) {
+            cols.in[c] = in[c0 + c];
+            cols.out[c] = out[c0 + c];
+        }
+        const int spw = 64 / m;
+        const long waves = ((long)g.V + spw - 1) / spw;
+        const unsigned nb = (unsigned)((waves + 3) / 4);
+        k_apply_sigma<OK_F64, EPI_NONE, 2><<<nb, 256, 0, st>>>(g, W, nullptr, nullptr, mhat, nullptr, nullptr, m,
+                                                               cols);
+        OK_LAUNCH_CHECK("k_apply_sigma");
+    }
     return OK_SUCCESS;
 }
 

@@ -226,6 +226,18 @@ def test_apply_sigma_layout_matches_oracle(lat, prec):
     assert rel(got, lat.apply(prec, psi)) <= (1e-14 if prec == 0 else 1e-6)
 
 
+def test_apply_sigma_f64_columns(lat):
+    """FP64 sigma W on five [V][12] fields (one pass of four with W read once, then one): each
+    against the oracle (FP64 bar) and against the one-at-a-time kernel."""
+    ok = lib()
+    psi = I.gaussian_sources(lat.dims, 5, 45)
+    got = lat.apply(ok.OK_F64 | SIGMA, psi)
+    ref = lat.oracle_B.apply(psi)
+    for k in range(5):
+        assert rel(got[k], ref[k]) <= TOL_APPLY[0]
+        assert rel(got[k], lat.apply(ok.OK_F64 | SIGMA, psi[k])) <= 1e-15
+
+
 @pytest.mark.parametrize("nrhs", [1, 5, 12, 16])
 def test_apply_sigma_rhs_inner_matches_single(lat, nrhs):
     """FP32 sigma W on nrhs right-hand-side-inner fields (the batched solver's operator): every
