@@ -379,7 +379,8 @@ def mixed(args):
     c = cfg["coeffs"]
     links = ok.to_device_complex(cfg["U"])
     Ws = {}
-    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
+    SIGMA = ok.OK_LAYOUT_SIGMA
+    for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16, ok.OK_F64 | SIGMA, ok.OK_F32 | SIGMA):
         Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(dims, prec))
         scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(dims))
         ok.ok_precompute_W(dims, c, links, prec, Ws[prec], scr)
@@ -389,7 +390,8 @@ def mixed(args):
            "workload": "%dx%dx%dx%d, plaquette 0.6 links, one Gaussian source" % dims, "n_gpus": 1,
            "unit": "s", "forms": {}}
     sol = {}
-    for name, low in (("plain_f64", None), ("mixed_f32", ok.OK_F32), ("mixed_bf16", ok.OK_BF16)):
+    for name, low, w64 in (("plain_f64", None, 0), ("mixed_f32", ok.OK_F32, 0), ("mixed_bf16", ok.OK_BF16, 0),
+                           ("plain_f64_sigma", None, SIGMA), ("mixed_f32_sigma", ok.OK_F32 | SIGMA, SIGMA)):
         lp = -1 if low is None else low
         work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(dims, 1, lp))
         best = None
@@ -397,7 +399,7 @@ def mixed(args):
             psi = torch.zeros_like(xi)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10), Ws[ok.OK_F64],
+            rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10, W64_layout=w64), Ws[ok.OK_F64 | w64],
                                     None if low is None else Ws[low], lp, xi, psi, 1, work)
             torch.cuda.synchronize()
             sec = time.perf_counter() - t
@@ -407,7 +409,7 @@ def mixed(args):
                               "reliable_updates": st[0]["reliable_updates"],
                               "true_rel_resid": st[0]["true_rel_resid"]}
         log("%s %s" % (name, out["forms"][name]))
-    for name in ("mixed_f32", "mixed_bf16"):
+    for name in ("mixed_f32", "mixed_bf16", "plain_f64_sigma", "mixed_f32_sigma"):
         err = float(torch.linalg.vector_norm(sol[name] - sol["plain_f64"]) /
                     torch.linalg.vector_norm(sol["plain_f64"]))
         out["forms"][name]["rel_error_vs_plain_f64"] = err
