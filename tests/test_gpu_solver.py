@@ -332,13 +332,14 @@ def test_16x16x16x32_mixed_vs_plain_full_size():
         assert err < 1e-8
 
 
-def test_batched_with_network_two_groups(learned_small):
+@pytest.mark.parametrize("low", [2 | 0x10, 1 | 0x200 | 0x20], ids=["bf16-site", "f32-sigma"])
+def test_batched_with_network_two_groups(learned_small, low):
     """20 right-hand sides (groups of 16 and 4) preconditioned by the network, one of them zero."""
     ok = lib()
     L = learned_small
     xi = I.gaussian_sources(L.dims, 20, 75)
     xi[7] = 0.0
-    rc, st, x = solve(L, xi, low=ok.OK_BF16 | SITE, net=L.net)
+    rc, st, x = solve(L, xi, low=low, net=L.net, w64=SIGMA if low & 0x200 else 0)
     assert rc == ok.OK_SUCCESS
     assert np.all(x[7] == 0) and st[7]["iterations"] == 0
     for k in range(20):
