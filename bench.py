@@ -98,7 +98,8 @@ def is_apply_kernel(name, form, kernel="k_apply"):
         return ("k_apply_saved<%d, 0>" % p) in name or ("k_apply_savedILi%dELi0E" % p) in name
     if kernel in ("k_apply_sigma", "k_apply_sigma_mr"):   # <prec, no epilogue, right-hand-side-inner>
         mr = 1 if kernel == "k_apply_sigma_mr" else 0
-        return ("k_apply_sigma<%d, 0, %d>" % (p, mr)) in name or ("k_apply_sigmaILi%dELi0ELi%dE" % (p, mr)) in name
+        head = "k_apply_sigma<%d, 0, %d" % (p, mr)   # followed by '>' or by the waves-per-SIMD argument
+        return (head + ">") in name or (head + ",") in name or ("k_apply_sigmaILi%dELi0ELi%dE" % (p, mr)) in name
     return any(("k_apply<%d, %d, 0>" % (p, t)) in name or ("k_applyILi%dELi%dELi0E" % (p, t)) in name
                for t in (1, 2, 4))
 
