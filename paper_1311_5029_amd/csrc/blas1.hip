@@ -39,178 +39,145 @@ __device__ __forceinline__ void dotacc(double2& d, cpx<T> a, cpx<T> b) {
     d.y += (double)a.re * b.im - (double)a.im * b.re;
 }
 
+// The vector kernels run one thread per complex component (ne = 12 V of them), so that
+// consecutive lanes touch consecutive addresses.
+
 // p = r + beta (p - omega v)
 template <typename T>
-__global__ void __launch_bounds__(BS) k_p_update(int n, T* p, const T* r, const T* v, const Scal* sc) {
-    const int s = blockIdx.x * BS + threadIdx.x;
-    if (s >= n) return;
+__global__ void __launch_bounds__(BS) k_p_update(long ne, T* p, const T* r, const T* v, const Scal* sc) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= ne) return;
     const cpx<T> beta = cast<T>(sc->beta), omega = cast<T>(sc->omega);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t)s * 12 + c;
-        cpx<T> pv = ld(p, i) - omega * ld(v, i);
-        st(p, i, ld(r, i) + beta * pv);
-    }
+    const cpx<T> pv = ld(p, i) - omega * ld(v, i);
+    st(p, i, ld(r, i) + beta * pv);
 }
 
 // s = r - alpha v
 template <typename T>
-__global__ void __launch_bounds__(BS) k_s_update(int n, T* s_, const T* r, const T* v, const Scal* sc) {
-    const int s = blockIdx.x * BS + threadIdx.x;
-    if (s >= n) return;
+__global__ void __launch_bounds__(BS) k_s_update(long ne, T* s_, const T* r, const T* v, const Scal* sc) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= ne) return;
     const cpx<T> alpha = cast<T>(sc->alpha);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t)s * 12 + c;
-        st(s_, i, ld(r, i) - alpha * ld(v, i));
-    }
+    st(s_, i, ld(r, i) - alpha * ld(v, i));
 }
 
 // x += alpha p + omega s ; r = s - omega t ; partial <r^, r>, <r, r>
 template <typename T>
-__global__ void __launch_bounds__(BS) k_xr_update(int n, T* x, T* r, const T* p, const T* sx, const T* s_,
+__global__ void __launch_bounds__(BS) k_xr_update(long ne, T* x, T* r, const T* p, const T* sx, const T* s_,
                                                   const T* t, const T* rhat, const Scal* sc, double2* partial) {
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
     double2 d1{0, 0}, d2{0, 0};
-    if (s < n) {
+    if (i < ne) {
         const cpx<T> alpha = cast<T>(sc->alpha), omega = cast<T>(sc->omega);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const size_t i = (size_t)s * 12 + c;
-            const cpx<T> sv = ld(s_, i);
-            st(x, i, ld(x, i) + alpha * ld(p, i) + omega * ld(sx, i));
-            const cpx<T> rv = sv - omega * ld(t, i);
-            st(r, i, rv);
-            dotacc(d1, ld(rhat, i), rv);
-            dotacc(d2, rv, rv);
-        }
+        const cpx<T> sv = ld(s_, i);
+        st(x, i, ld(x, i) + alpha * ld(p, i) + omega * ld(sx, i));
+        const cpx<T> rv = sv - omega * ld(t, i);
+        st(r, i, rv);
+        dotacc(d1, ld(rhat, i), rv);
+        dotacc(d2, rv, rv);
     }
     block_reduce2_store(d1, d2, partial);
 }
 
 // partial <a, b>, <b, b>
 template <typename T>
-__global__ void __launch_bounds__(BS) k_dot(int n, const T* a, const T* b, double2* partial) {
-    const int s = blockIdx.x * BS + threadIdx.x;
+__global__ void __launch_bounds__(BS) k_dot(long ne, const T* a, const T* b, double2* partial) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
     double2 d1{0, 0}, d2{0, 0};
-    if (s < n) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const size_t i = (size_t)s * 12 + c;
-            const cpx<T> bv = ld(b, i);
-            dotacc(d1, ld(a, i), bv);
-            dotacc(d2, bv, bv);
-        }
+    if (i < ne) {
+        const cpx<T> bv = ld(b, i);
+        dotacc(d1, ld(a, i), bv);
+        dotacc(d2, bv, bv);
     }
     block_reduce2_store(d1, d2, partial);
 }
 
 // r64 = xi - t64 ; rlo = (float) r64 ; partial <r64, r64> (in the second slot)
-__global__ void __launch_bounds__(BS) k_residual(int n, const double* xi, const double* t64, double* r64, float* rlo,
+__global__ void __launch_bounds__(BS) k_residual(long ne, const double* xi, const double* t64, double* r64, float* rlo,
                                                  double2* partial) {
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
     double2 d1{0, 0}, d2{0, 0};
-    if (s < n) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const size_t i = (size_t)s * 12 + c;
-            const c128 rv = ld(xi, i) - ld(t64, i);
-            st(r64, i, rv);
-            if (rlo) st(rlo, i, c64{(float)rv.re, (float)rv.im});
-            dotacc(d2, rv, rv);
-        }
+    if (i < ne) {
+        const c128 rv = ld(xi, i) - ld(t64, i);
+        st(r64, i, rv);
+        if (rlo) st(rlo, i, c64{(float)rv.re, (float)rv.im});
+        dotacc(d2, rv, rv);
     }
     block_reduce2_store(d1, d2, partial);
 }
 
-__global__ void __launch_bounds__(BS) k_accum_x(int n, double* x64, float* xlo) {
-    const int s = blockIdx.x * BS + threadIdx.x;
-    if (s >= n) return;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t)s * 12 + c;
-        const c64 l = ld(xlo, i);
-        st(x64, i, ld(x64, i) + c128{(double)l.re, (double)l.im});
-        st(xlo, i, c64{0.0f, 0.0f});
-    }
+__global__ void __launch_bounds__(BS) k_accum_x(long ne, double* x64, float* xlo) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= ne) return;
+    const c64 l = ld(xlo, i);
+    st(x64, i, ld(x64, i) + c128{(double)l.re, (double)l.im});
+    st(xlo, i, c64{0.0f, 0.0f});
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BS) k_copy(int n, T* dst, const T* src) {
-    const int s = blockIdx.x * BS + threadIdx.x;
-    if (s >= n) return;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) st(dst, (size_t)s * 12 + c, ld(src, (size_t)s * 12 + c));
+__global__ void __launch_bounds__(BS) k_copy(long ne, T* dst, const T* src) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i < ne) st(dst, i, ld(src, i));
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BS) k_zero(int n, T* dst) {
-    const int s = blockIdx.x * BS + threadIdx.x;
-    if (s >= n) return;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) st(dst, (size_t)s * 12 + c, cpx<T>{(T)0, (T)0});
+__global__ void __launch_bounds__(BS) k_zero(long ne, T* dst) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i < ne) st(dst, i, cpx<T>{(T)0, (T)0});
 }
 
 // ---- CG on the normal equations M^dag M x = M^dag xi (M^dag = gamma5 M gamma5) ----------
 // gamma5 = [[0, -i], [i, 0]] on the upper (spins 0, 1) and lower (spins 2, 3) spin pairs:
-// (gamma5 psi)_u = -i psi_d, (gamma5 psi)_d = i psi_u.
-__device__ __forceinline__ double2 g5_comp(const double2* f, size_t site, int c) {
-    const double2 o = f[site * 12 + (c + 6) % 12];
-    return c < 6 ? make_double2(o.y, -o.x) : make_double2(-o.y, o.x);   // -i o  |  i o
+// (gamma5 psi)_u = -i psi_d, (gamma5 psi)_d = i psi_u.  Component c of a site pairs with
+// component (c + 6) % 12 of the same site.
+__device__ __forceinline__ long g5_partner(long i) {
+    const int c = (int)(i % 12);
+    return i - c + (c + 6) % 12;
+}
+// the entry at the partner of component i that gamma5 makes from the value o at i
+__device__ __forceinline__ double2 g5_to_partner(long i, double2 o) {
+    return (i % 12) < 6 ? make_double2(-o.y, o.x) : make_double2(o.y, -o.x);   // i o (lower)  |  -i o (upper)
 }
 
 // g = gamma5 r ; partial (0, ||r||^2)
-__global__ void __launch_bounds__(BS) k_cg_gamma5(int n, double2* g, const double2* r, double2* partial) {
-    const int s = blockIdx.x * BS + threadIdx.x;
+__global__ void __launch_bounds__(BS) k_cg_gamma5(long ne, double2* g, const double2* r, double2* partial) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
     double2 d{0, 0};
-    if (s < n) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const double2 v = r[(size_t)s * 12 + c];
-            d.x += v.x * v.x + v.y * v.y;
-            g[(size_t)s * 12 + c] = g5_comp(r, s, c);
-        }
+    if (i < ne) {
+        const double2 v = r[i];
+        d.x = v.x * v.x + v.y * v.y;
+        g[g5_partner(i)] = g5_to_partner(i, v);
     }
     block_reduce2_store(double2{0, 0}, d, partial);
 }
 
-// x += alpha p ; r -= alpha w ; g = gamma5 r ; partial (0, ||r||^2)   (alpha real)
-__global__ void __launch_bounds__(BS) k_cg_xr(int n, double2* x, double2* r, const double2* p, const double2* w,
+// x += alpha p ; r -= alpha w ; g = gamma5 r ; partial (0, ||r||^2)   (alpha real).  Each thread
+// writes the gamma5 entry its new r makes at the partner component, so no thread reads an r that
+// another one updates.
+__global__ void __launch_bounds__(BS) k_cg_xr(long ne, double2* x, double2* r, const double2* p, const double2* w,
                                               double2* g, const Scal* sc, double2* partial) {
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
     double2 d{0, 0};
-    if (s < n) {
+    if (i < ne) {
         const double a = sc->alpha.x;
-        double2 rn[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const size_t i = (size_t)s * 12 + c;
-            const double2 pv = p[i], wv = w[i], xv = x[i], rv = r[i];
-            x[i] = make_double2(fma(a, pv.x, xv.x), fma(a, pv.y, xv.y));
-            rn[c] = make_double2(fma(-a, wv.x, rv.x), fma(-a, wv.y, rv.y));
-            r[i] = rn[c];
-            d.x += rn[c].x * rn[c].x + rn[c].y * rn[c].y;
-        }
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const double2 o = rn[(c + 6) % 12];
-            g[(size_t)s * 12 + c] = c < 6 ? make_double2(o.y, -o.x) : make_double2(-o.y, o.x);
-        }
+        const double2 pv = p[i], wv = w[i], xv = x[i], rv = r[i];
+        x[i] = make_double2(fma(a, pv.x, xv.x), fma(a, pv.y, xv.y));
+        const double2 rn = make_double2(fma(-a, wv.x, rv.x), fma(-a, wv.y, rv.y));
+        r[i] = rn;
+        d.x = rn.x * rn.x + rn.y * rn.y;
+        g[g5_partner(i)] = g5_to_partner(i, rn);
     }
     block_reduce2_store(double2{0, 0}, d, partial);
 }
 
 // p = gamma5 z' + beta p   (beta real; z' = M gamma5 r, so gamma5 z' = M^dag r)
-__global__ void __launch_bounds__(BS) k_cg_p(int n, double2* p, const double2* zp, const Scal* sc) {
-    const int s = blockIdx.x * BS + threadIdx.x;
-    if (s >= n) return;
+__global__ void __launch_bounds__(BS) k_cg_p(long ne, double2* p, const double2* zp, const Scal* sc) {
+    const long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= ne) return;
     const double b = sc->beta.x;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t)s * 12 + c;
-        const double2 z = g5_comp(zp, s, c), pv = p[i];
-        p[i] = make_double2(fma(b, pv.x, z.x), fma(b, pv.y, z.y));
-    }
+    const long j = g5_partner(i);
+    const double2 z = g5_to_partner(j, zp[j]), pv = p[i];
+    p[i] = make_double2(fma(b, pv.x, z.x), fma(b, pv.y, z.y));
 }
 
 // One block: fixed-order reduction of nb partial pairs, then the scalar update.
@@ -315,21 +282,21 @@ __global__ void __launch_bounds__(BS) k_finish(int kind, int nb, const double2* 
 
 }  // namespace
 
-int blas_blocks(const Geo& g) { return (int)grid_for(g.V, BS); }
+int blas_blocks(const Geo& g) { return (int)grid_for(12L * g.V, BS); }
 
 template <typename T> static T* tp(void* p) { return reinterpret_cast<T*>(p); }
 template <typename T> static const T* tp(const void* p) { return reinterpret_cast<const T*>(p); }
 
 int launch_p_update(const Geo& g, bool f64, void* p, const void* r, const void* v, const Scal* sc, hipStream_t st) {
-    if (f64) k_p_update<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(p), tp<double>(r), tp<double>(v), sc);
-    else k_p_update<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(p), tp<float>(r), tp<float>(v), sc);
+    if (f64) k_p_update<double><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<double>(p), tp<double>(r), tp<double>(v), sc);
+    else k_p_update<float><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<float>(p), tp<float>(r), tp<float>(v), sc);
     OK_LAUNCH_CHECK("k_p_update");
     return OK_SUCCESS;
 }
 
 int launch_s_update(const Geo& g, bool f64, void* s, const void* r, const void* v, const Scal* sc, hipStream_t st) {
-    if (f64) k_s_update<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(s), tp<double>(r), tp<double>(v), sc);
-    else k_s_update<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(s), tp<float>(r), tp<float>(v), sc);
+    if (f64) k_s_update<double><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<double>(s), tp<double>(r), tp<double>(v), sc);
+    else k_s_update<float><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<float>(s), tp<float>(r), tp<float>(v), sc);
     OK_LAUNCH_CHECK("k_s_update");
     return OK_SUCCESS;
 }
@@ -337,11 +304,11 @@ int launch_s_update(const Geo& g, bool f64, void* s, const void* r, const void* 
 int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, const void* sx, const void* s,
                      const void* t, const void* rhat, const Scal* sc, double2* partial, hipStream_t st) {
     if (f64)
-        k_xr_update<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(x), tp<double>(r), tp<double>(p),
+        k_xr_update<double><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<double>(x), tp<double>(r), tp<double>(p),
                                                               tp<double>(sx), tp<double>(s), tp<double>(t),
                                                               tp<double>(rhat), sc, partial);
     else
-        k_xr_update<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(x), tp<float>(r), tp<float>(p),
+        k_xr_update<float><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<float>(x), tp<float>(r), tp<float>(p),
                                                              tp<float>(sx), tp<float>(s), tp<float>(t),
                                                              tp<float>(rhat), sc, partial);
     OK_LAUNCH_CHECK("k_xr_update");
@@ -349,14 +316,14 @@ int launch_xr_update(const Geo& g, bool f64, void* x, void* r, const void* p, co
 }
 
 int launch_dot_rr(const Geo& g, bool f64, const void* rhat, const void* r, double2* partial, hipStream_t st) {
-    if (f64) k_dot<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(rhat), tp<double>(r), partial);
-    else k_dot<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(rhat), tp<float>(r), partial);
+    if (f64) k_dot<double><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<double>(rhat), tp<double>(r), partial);
+    else k_dot<float><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<float>(rhat), tp<float>(r), partial);
     OK_LAUNCH_CHECK("k_dot");
     return OK_SUCCESS;
 }
 
 int launch_norm64(const Geo& g, const double* a, double2* partial, hipStream_t st) {
-    k_dot<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, a, a, partial);
+    k_dot<double><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, a, a, partial);
     OK_LAUNCH_CHECK("k_dot");
     return OK_SUCCESS;
 }
@@ -369,33 +336,33 @@ int launch_finish(int kind, int nblocks, const double2* partial, Scal* sc, hipSt
 
 int launch_residual(const Geo& g, const double* xi, const double* t64, double* r64, float* rlo, double2* partial,
                     hipStream_t st) {
-    k_residual<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, xi, t64, r64, rlo, partial);
+    k_residual<<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, xi, t64, r64, rlo, partial);
     OK_LAUNCH_CHECK("k_residual");
     return OK_SUCCESS;
 }
 
 int launch_accum_x(const Geo& g, double* x64, float* xlo, hipStream_t st) {
-    k_accum_x<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, x64, xlo);
+    k_accum_x<<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, x64, xlo);
     OK_LAUNCH_CHECK("k_accum_x");
     return OK_SUCCESS;
 }
 
 int launch_copy(const Geo& g, bool f64, void* dst, const void* src, hipStream_t st) {
-    if (f64) k_copy<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(dst), tp<double>(src));
-    else k_copy<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(dst), tp<float>(src));
+    if (f64) k_copy<double><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<double>(dst), tp<double>(src));
+    else k_copy<float><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<float>(dst), tp<float>(src));
     OK_LAUNCH_CHECK("k_copy");
     return OK_SUCCESS;
 }
 
 int launch_zero(const Geo& g, bool f64, void* dst, hipStream_t st) {
-    if (f64) k_zero<double><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<double>(dst));
-    else k_zero<float><<<grid_for(g.V, BS), BS, 0, st>>>(g.V, tp<float>(dst));
+    if (f64) k_zero<double><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<double>(dst));
+    else k_zero<float><<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, tp<float>(dst));
     OK_LAUNCH_CHECK("k_zero");
     return OK_SUCCESS;
 }
 
 int launch_cg_gamma5(const Geo& g, double* out, const double* r, double2* partial, hipStream_t st) {
-    k_cg_gamma5<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, reinterpret_cast<double2*>(out),
+    k_cg_gamma5<<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, reinterpret_cast<double2*>(out),
                                                    reinterpret_cast<const double2*>(r), partial);
     OK_LAUNCH_CHECK("k_cg_gamma5");
     return OK_SUCCESS;
@@ -403,7 +370,7 @@ int launch_cg_gamma5(const Geo& g, double* out, const double* r, double2* partia
 
 int launch_cg_xr(const Geo& g, double* x, double* r, const double* p, const double* w, double* gr, const Scal* sc,
                  double2* partial, hipStream_t st) {
-    k_cg_xr<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, reinterpret_cast<double2*>(x), reinterpret_cast<double2*>(r),
+    k_cg_xr<<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, reinterpret_cast<double2*>(x), reinterpret_cast<double2*>(r),
                                                reinterpret_cast<const double2*>(p), reinterpret_cast<const double2*>(w),
                                                reinterpret_cast<double2*>(gr), sc, partial);
     OK_LAUNCH_CHECK("k_cg_xr");
@@ -411,7 +378,7 @@ int launch_cg_xr(const Geo& g, double* x, double* r, const double* p, const doub
 }
 
 int launch_cg_p(const Geo& g, double* p, const double* zp, const Scal* sc, hipStream_t st) {
-    k_cg_p<<<grid_for(g.V, BS), BS, 0, st>>>(g.V, reinterpret_cast<double2*>(p), reinterpret_cast<const double2*>(zp),
+    k_cg_p<<<grid_for(12L * g.V, BS), BS, 0, st>>>(12L * g.V, reinterpret_cast<double2*>(p), reinterpret_cast<const double2*>(zp),
                                               sc);
     OK_LAUNCH_CHECK("k_cg_p");
     return OK_SUCCESS;
