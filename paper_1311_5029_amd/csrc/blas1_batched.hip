@@ -261,7 +261,77 @@ __global__ void __launch_bounds__(BS) kb_col_dot(int rows, int nrhs, int j, cons
     col_slot_store(d1, d2, partial, j);
 }
 
+// ---- several columns at once (the grouped reliable updates): one thread per (row, slot) as above,
+// working on the right-hand sides j whose bit is set in mask (or whose slot[j] >= 0); the FP64
+// fields of column j are at base + j * col (col complex numbers per column).
+
+// x64_j += x32[:, j] ; x32[:, j] = 0
+__global__ void __launch_bounds__(BS) kb_cols_accum(int rows, int nrhs, unsigned mask, double* x64, size_t col,
+                                                    float* x32) {
+    const int j = threadIdx.x & 15;
+    if (j >= nrhs || !((mask >> j) & 1u)) return;
+    c128* xj = reinterpret_cast<c128*>(x64) + (size_t)j * col;
+    for (int row = blockIdx.x * 16 + (threadIdx.x >> 4); row < rows; row += gridDim.x * 16) {
+        const size_t i = (size_t)row * nrhs + j;
+        const c64 l = ldc(x32, i);
+        xj[row] = xj[row] + c128{(double)l.re, (double)l.im};
+        stc(x32, i, c64{0.f, 0.f});
+    }
+}
+
+// r32[:, j] = xi_j - t64[slot j] ; partial (0, |r_j|^2) for every j with slot j >= 0
+__global__ void __launch_bounds__(BS) kb_cols_residual(int rows, int nrhs, ColSlots sl, const double* xi, size_t col,
+                                                       const double* t64, float* r32, double2* partial) {
+    const int j = threadIdx.x & 15;
+    const int slot = j < nrhs ? sl.slot[j] : -1;
+    double2 d1{0, 0}, d2{0, 0};
+    if (slot >= 0) {
+        const c128* x = reinterpret_cast<const c128*>(xi) + (size_t)j * col;
+        const c128* t = reinterpret_cast<const c128*>(t64) + (size_t)slot * col;
+        for (int row = blockIdx.x * 16 + (threadIdx.x >> 4); row < rows; row += gridDim.x * 16) {
+            const c128 v = x[row] - t[row];
+            stc(r32, (size_t)row * nrhs + j, c64{(float)v.re, (float)v.im});
+            d2.x += v.re * v.re + v.im * v.im;
+        }
+    }
+    slot_reduce_store(d1, d2, partial, nrhs);
+}
+
+// partial <a_j, b_j>, <b_j, b_j> for every j in mask
+__global__ void __launch_bounds__(BS) kb_cols_dot(int rows, int nrhs, unsigned mask, const float* a, const float* b,
+                                                  double2* partial) {
+    const int j = threadIdx.x & 15;
+    double2 d1{0, 0}, d2{0, 0};
+    if (j < nrhs && ((mask >> j) & 1u)) {
+        for (int row = blockIdx.x * 16 + (threadIdx.x >> 4); row < rows; row += gridDim.x * 16) {
+            const size_t i = (size_t)row * nrhs + j;
+            const c64 bv = ldc(b, i);
+            dacc(d1, ldc(a, i), bv);
+            dacc(d2, bv, bv);
+        }
+    }
+    slot_reduce_store(d1, d2, partial, nrhs);
+}
+
 }  // namespace
+
+int launch_cols_accum(const Geo& g, int nrhs, unsigned mask, double* x64, float* x32, hipStream_t st) {
+    kb_cols_accum<<<kGridB, BS, 0, st>>>(batch_rows(g), nrhs, mask, x64, (size_t)g.V * 12, x32);
+    OK_LAUNCH_CHECK("kb_cols_accum");
+    return OK_SUCCESS;
+}
+int launch_cols_residual(const Geo& g, int nrhs, const ColSlots& sl, const double* xi, const double* t64, float* r32,
+                         double2* partial, hipStream_t st) {
+    kb_cols_residual<<<kGridB, BS, 0, st>>>(batch_rows(g), nrhs, sl, xi, (size_t)g.V * 12, t64, r32, partial);
+    OK_LAUNCH_CHECK("kb_cols_residual");
+    return OK_SUCCESS;
+}
+int launch_cols_dot(const Geo& g, int nrhs, unsigned mask, const float* a, const float* b, double2* partial,
+                    hipStream_t st) {
+    kb_cols_dot<<<kGridB, BS, 0, st>>>(batch_rows(g), nrhs, mask, a, b, partial);
+    OK_LAUNCH_CHECK("kb_cols_dot");
+    return OK_SUCCESS;
+}
 
 int batch_rows(const Geo& g) { return g.V * 12; }
 int col_blocks(const Geo& g) { return (int)grid_for((long)g.V * 12, BS); }

@@ -142,6 +142,16 @@ int launch_bdot(const Geo& g, int nrhs, const float* a, const float* b, const Sc
                 hipStream_t st);
 int launch_bfinish(int kind, int nblocks, int j0, int nj, const double2* partial, ScalB* sc, hipStream_t st);
 int launch_col_accum(const Geo& g, int nrhs, int j, double* x64, float* x32, hipStream_t st);
+// several columns per kernel (fixed kGridB grid; partials as launch_bdot): x64 is the base of the
+// [nrhs][V][12] FP64 fields, column j's FP64 residual input at t64 + slot[j] * 12 V
+struct ColSlots {
+    int slot[kMaxRhsB];   // -1: column not in this pass
+};
+int launch_cols_accum(const Geo& g, int nrhs, unsigned mask, double* x64, float* x32, hipStream_t st);
+int launch_cols_residual(const Geo& g, int nrhs, const ColSlots& sl, const double* xi, const double* t64, float* r32,
+                         double2* partial, hipStream_t st);
+int launch_cols_dot(const Geo& g, int nrhs, unsigned mask, const float* a, const float* b, double2* partial,
+                    hipStream_t st);
 int launch_col_residual(const Geo& g, int nrhs, int j, const double* xi, const double* t64, float* r32,
                         double2* partial, hipStream_t st);
 int launch_col_norm64(const Geo& g, int j, const double* a, double2* partial, hipStream_t st);

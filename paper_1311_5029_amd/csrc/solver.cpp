@@ -464,7 +464,9 @@ int batched_true_residuals(Ctx& C, WorkB& B, int nrhs, const int* cols, int n, c
                            double* rr, ok_solver_stats* S) {
     const Geo& g = C.g;
     const size_t col = (size_t)g.V * 24;
-    for (int i = 0; i < n; ++i) OK_TRY(launch_col_accum(g, nrhs, cols[i], x + cols[i] * col, B.f[0], C.st));
+    unsigned mask = 0;
+    for (int i = 0; i < n; ++i) mask |= 1u << cols[i];
+    OK_TRY(launch_cols_accum(g, nrhs, mask, x, B.f[0], C.st));
     for (int i0 = 0; i0 < n; i0 += 4) {
         const int m = std::min(4, n - i0);
         const double* in[4];
@@ -482,11 +484,14 @@ int batched_true_residuals(Ctx& C, WorkB& B, int nrhs, const int* cols, int n, c
                 OK_TRY(launch_apply(g, C.W64, C.W64_prec, in[r], out[r], C.c->mhat, 1, EPI_NONE, nullptr, nullptr,
                                     C.st));
         }
+        ColSlots sl;
+        for (int j = 0; j < kMaxRhsB; ++j) sl.slot[j] = -1;
+        for (int r = 0; r < m; ++r) sl.slot[cols[i0 + r]] = r;
+        OK_TRY(launch_cols_residual(g, nrhs, sl, xi, B.t64, B.f[1], B.partial, C.st));
         for (int r = 0; r < m; ++r) {
             const int j = cols[i0 + r];
             S[j].matvec_hi++;
-            OK_TRY(launch_col_residual(g, nrhs, j, xi + j * col, out[r], B.f[1], B.partial, C.st));
-            OK_TRY(bfin(C, B, FIN_TRUE, col_blocks(g), j, 1));
+            OK_TRY(bfin(C, B, FIN_TRUE, kGridB, j, 1));
         }
     }
     ScalB h;
@@ -647,6 +652,7 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
                 if (h.active[j] && (due[j] || rnv[j] < dg * maxr[j])) cols[n++] = j;
             double rrv[kMaxRhsB];
             OK_TRY(batched_true_residuals(C, B, nrhs, cols, n, xi, x, rrv, S));
+            unsigned replace = 0;   // columns that continue from the new residual: rho = <r^, r>
             for (int i = 0; i < n; ++i) {
                 const int j = cols[i];
                 const bool broke = hd.flags[j] & 1;
@@ -671,9 +677,13 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
                     S[j].restarts++;
                     OK_TRY(batched_restart(C, B, nrhs, j));
                 } else {
-                    OK_TRY(launch_col_dot(g, nrhs, j, rhat, r, B.partial, C.st));
-                    OK_TRY(bfin(C, B, FIN_RHO_REPLACE, col_blocks(g), j, 1));
+                    replace |= 1u << j;
                 }
+            }
+            if (replace) {   // a restart touches only its own column, so these dots can come after
+                OK_TRY(launch_cols_dot(g, nrhs, replace, rhat, r, B.partial, C.st));
+                for (int j = 0; j < nrhs; ++j)
+                    if ((replace >> j) & 1u) OK_TRY(bfin(C, B, FIN_RHO_REPLACE, kGridB, j, 1));
             }
         }
         if (changed) OK_TRY(write_active(C, B, &h));
