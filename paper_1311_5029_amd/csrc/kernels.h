@@ -56,9 +56,13 @@ int stencil_tps(int Wprec);
 int apply_blocks(const Geo& g, int tps);
 int launch_apply(const Geo& g, const void* W, int Wprec, const void* psi, void* out, double mhat, int tps,
                  int epi, const void* aux, double2* partial, hipStream_t st);
-// FP32 sigma-layout W on nrhs (<= 16) right-hand sides stored [V][12][nrhs] (no epilogue)
+// FP32 sigma-layout W on nrhs (<= 16) right-hand sides stored [V][12][nrhs]; with epi EPI_RV the
+// per-right-hand-side partials <aux, out>, with EPI_TS <out, aux>, <out, out>, in
+// partial[block][j][2] over sigma_mr_blocks blocks (the batched solver's layout)
+int sigma_mr_blocks(const Geo& g, int nrhs);
 int launch_apply_sigma_mr(const Geo& g, const void* W, const float* psi, float* out, double mhat, int nrhs,
-                          hipStream_t st);
+                          hipStream_t st, int epi = EPI_NONE, const float* aux = nullptr,
+                          double2* partial = nullptr);
 // FP64 sigma-layout W on n separate [V][12] fields, up to four per pass (W read once per pass)
 int launch_apply_sigma_cols(const Geo& g, const void* W, const double* const* in, double* const* out, int n,
                             double mhat, hipStream_t st);

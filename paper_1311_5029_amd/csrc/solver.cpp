@@ -427,7 +427,7 @@ size_t layout_batched(const Geo& g, int nrhs, int net_layers, char* base, WorkB*
     WorkB tmp;
     WorkB& W = w ? *w : tmp;
     W.sc = reinterpret_cast<ScalB*>(take(sizeof(ScalB)));
-    const int nb = std::max(kGridB, col_blocks(g));
+    const int nb = std::max({kGridB, col_blocks(g), sigma_mr_blocks(g, kMaxRhsB)});
     W.partial = reinterpret_cast<double2*>(take((size_t)nb * kMaxRhsB * 2 * sizeof(double2)));
     W.t64 = reinterpret_cast<double*>(take((size_t)4 * g.V * 12 * 16));   // four FP64 fields
     for (int i = 0; i < (net_layers ? 9 : 7); ++i) W.f[i] = reinterpret_cast<float*>(take((size_t)g.V * 12 * nrhs * 8));
@@ -593,14 +593,25 @@ int solve_batched(Ctx& C, WorkB& B, int nrhs, const double* xi, double* x, ok_so
         float* sh = C.net ? B.f[8] : s;
         OK_TRY(launch_bp_update(g, nrhs, p, r, v, B.sc, C.st));
         if (C.net) OK_TRY(apply_net(C, p, ph, nrhs, true, B.netw));
-        OK_TRY(apply_lo_batched(C, ph, v, nrhs));
-        OK_TRY(launch_bdot(g, nrhs, rhat, v, B.sc, B.partial, C.st));
-        OK_TRY(bfin(C, B, FIN_ALPHA, kGridB, 0, nrhs));
+        const bool sig = (C.Wlo_prec & OK_LAYOUT_SIGMA) != 0;   // its epilogue forms the dots
+        if (sig) {
+            OK_TRY(launch_apply_sigma_mr(g, C.Wlo, ph, v, C.c->mhat, nrhs, C.st, EPI_RV, rhat, B.partial));
+            OK_TRY(bfin(C, B, FIN_ALPHA, sigma_mr_blocks(g, nrhs), 0, nrhs));
+        } else {
+            OK_TRY(apply_lo_batched(C, ph, v, nrhs));
+            OK_TRY(launch_bdot(g, nrhs, rhat, v, B.sc, B.partial, C.st));
+            OK_TRY(bfin(C, B, FIN_ALPHA, kGridB, 0, nrhs));
+        }
         OK_TRY(launch_bs_update(g, nrhs, s, r, v, B.sc, C.st));
         if (C.net) OK_TRY(apply_net(C, s, sh, nrhs, true, B.netw));
-        OK_TRY(apply_lo_batched(C, sh, t, nrhs));
-        OK_TRY(launch_bdot(g, nrhs, t, s, B.sc, B.partial, C.st));
-        OK_TRY(bfin(C, B, FIN_OMEGA, kGridB, 0, nrhs));
+        if (sig) {
+            OK_TRY(launch_apply_sigma_mr(g, C.Wlo, sh, t, C.c->mhat, nrhs, C.st, EPI_TS, s, B.partial));
+            OK_TRY(bfin(C, B, FIN_OMEGA, sigma_mr_blocks(g, nrhs), 0, nrhs));
+        } else {
+            OK_TRY(apply_lo_batched(C, sh, t, nrhs));
+            OK_TRY(launch_bdot(g, nrhs, t, s, B.sc, B.partial, C.st));
+            OK_TRY(bfin(C, B, FIN_OMEGA, kGridB, 0, nrhs));
+        }
         OK_TRY(launch_bxr_update(g, nrhs, x32, r, ph, sh, s, t, rhat, B.sc, B.partial, C.st));
         OK_TRY(bfin(C, B, FIN_RHO, kGridB, 0, nrhs));
         ScalB hd;

@@ -252,6 +252,31 @@ __device__ __forceinline__ void ld_sp(const T* __restrict__ psi, int s, cpx<T> v
     for (int q = 0; q < 12; ++q) v[q] = nr ? p[((size_t)s * 12 + q) * nr + r] : p[(size_t)s * 12 + q];
 }
 
+// Per right-hand side of a block of the MR == 1 kernel: the lanes of right-hand side r (slot k of
+// wavefront w is lane 64 w + k nr + r) summed in a fixed order, stored as partial[block][r][2]
+// (the layout of the batched solver's reductions).
+__device__ __forceinline__ void rhs_reduce_store(double2 d1, double2 d2, double2* partial, int nr) {
+    __shared__ double2 red[2][256];
+    red[0][threadIdx.x] = d1;
+    red[1][threadIdx.x] = d2;
+    __syncthreads();
+    if ((int)threadIdx.x < nr) {
+        const int r = threadIdx.x, spw = 64 / nr;
+        double2 a{0.0, 0.0}, b{0.0, 0.0};
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            for (int k = 0; k < spw; ++k) {
+                const int l = w * 64 + k * nr + r;
+                a.x += red[0][l].x;
+                a.y += red[0][l].y;
+                b.x += red[1][l].x;
+                b.y += red[1][l].y;
+            }
+        double2* p = partial + ((size_t)blockIdx.x * kMaxRhsB + r) * 2;
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
 // Up to four separate [V][12] fields (MR == 2).
 template <typename T>
 struct SCols {
@@ -354,26 +379,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
         for (int q = 0; q < 12; ++q)
             o[MR == 1 ? ((size_t)s * 12 + q) * nr + r : (size_t)s * 12 + q] = acc[q / 6][(q / 3) & 1][q % 3];
+        // epilogue dots; with MR == 1 over this lane's right-hand side, the second vector of
+        // <t, s> given in aux (the solver's s, which is not the operator's input when it is
+        // preconditioned)
+        const cpx<T>* ax = reinterpret_cast<const cpx<T>*>(aux);
+        const cpx<T>* ps = reinterpret_cast<const cpx<T>*>(psi);
+        auto at = [&](const cpx<T>* f, int q) __attribute__((always_inline)) {
+            return MR == 1 ? f[((size_t)s * 12 + q) * nr + r] : f[(size_t)s * 12 + q];
+        };
         if constexpr (EPI == EPI_RV) {
-            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(aux) + (size_t)s * 12;
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                const cpx<T> av = a[q], w = acc[q / 6][(q / 3) & 1][q % 3];
+                const cpx<T> av = at(ax, q), w = acc[q / 6][(q / 3) & 1][q % 3];
                 d1.x += (double)av.re * w.re + (double)av.im * w.im;
                 d1.y += (double)av.re * w.im - (double)av.im * w.re;
             }
         } else if constexpr (EPI == EPI_TS) {
-            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12;
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                const cpx<T> sv = a[q], w = acc[q / 6][(q / 3) & 1][q % 3];
+                const cpx<T> sv = at(MR == 1 ? ax : ps, q), w = acc[q / 6][(q / 3) & 1][q % 3];
                 d1.x += (double)w.re * sv.re + (double)w.im * sv.im;
                 d1.y += (double)w.re * sv.im - (double)w.im * sv.re;
                 d2.x += (double)w.re * w.re + (double)w.im * w.im;
             }
         }
     }
-    if constexpr (EPI != EPI_NONE) block_reduce2_store(d1, d2, partial);
+    if constexpr (EPI != EPI_NONE) {
+        if constexpr (MR == 1) rhs_reduce_store(d1, d2, partial, nr);
+        else block_reduce2_store(d1, d2, partial);
+    }
 }
 
 template <int P>
@@ -394,17 +428,26 @@ int launch_sigma_t(const Geo& g, const void* W, const void* psi, void* out, doub
 
 }  // namespace
 
+int sigma_mr_blocks(const Geo& g, int nrhs) {
+    const int spw = 64 / nrhs;
+    const long waves = ((long)g.V + spw - 1) / spw;
+    return (int)((waves + 3) / 4);
+}
+
 int launch_apply_sigma_mr(const Geo& g, const void* W, const float* psi, float* out, double mhat, int nrhs,
-                          hipStream_t st) {
+                          hipStream_t st, int epi, const float* aux, double2* partial) {
     if (nrhs < 1 || nrhs > 16) {
         set_error("right-hand-side-inner spinors support 1 to 16 right-hand sides");
         return OK_EINVAL;
     }
-    const int spw = 64 / nrhs;
-    const long waves = ((long)g.V + spw - 1) / spw;
-    const unsigned nb = (unsigned)((waves + 3) / 4);
-    k_apply_sigma<OK_F32, EPI_NONE, 1><<<nb, 256, 0, st>>>(g, W, psi, out, mhat, nullptr, nullptr, nrhs,
-                                                           SCols<float>{});
+    const unsigned nb = (unsigned)sigma_mr_blocks(g, nrhs);
+    if (epi == EPI_RV)
+        k_apply_sigma<OK_F32, EPI_RV, 1><<<nb, 256, 0, st>>>(g, W, psi, out, mhat, aux, partial, nrhs, SCols<float>{});
+    else if (epi == EPI_TS)
+        k_apply_sigma<OK_F32, EPI_TS, 1><<<nb, 256, 0, st>>>(g, W, psi, out, mhat, aux, partial, nrhs, SCols<float>{});
+    else
+        k_apply_sigma<OK_F32, EPI_NONE, 1><<<nb, 256, 0, st>>>(g, W, psi, out, mhat, nullptr, nullptr, nrhs,
+                                                               SCols<float>{});
     OK_LAUNCH_CHECK("k_apply_sigma");
     return OK_SUCCESS;
 }
