@@ -118,17 +118,7 @@ class WForm:
             S = S + c.c_3 / (2.0 * u0 ** 4) * (Uc @ si @ shift(BD, i, 1) - si @ BD @ Uc
                                                + colour(2j * Bi @ Ui))
             Dm = -0.5 * (c.r_s * c.zeta + 8.0 * c.c_4) * Uc
-            stap = 0.0
-            for j in range(3):
-                for k in range(3):
-                    e = _eps(i, j, k)
-                    if e == 0:
-                        continue
-                    Uk = link(U, k)
-                    up = Uk @ shift(Ui, k, 1) @ dag(shift(Uk, i, 1))
-                    dn = dag(shift(Uk, k, -1)) @ shift(Ui, k, -1) @ shift(shift(Uk, k, -1), i, 1)
-                    stap = stap + e * kron2(SIGMA[j], up - dn)
-            Dm = Dm + 1j * c.c_5 / 4.0 * (u0 ** -2 - u0 ** -4) * stap
+            Dm = Dm + 1j * c.c_5 / 4.0 * (u0 ** -2 - u0 ** -4) * self._eps_staple(i)
             Dm = Dm + c.c_5 / u0 ** 4 * (Uc @ shift(BD, i, 1) + BD @ Uc
                                          - 1j * kron2(SIGMA[i], Ui @ shift(Bi, i, 1) + Bi @ Ui))
             W[1 + i] = blocks(Dm, S, S, Dm)
@@ -144,6 +134,23 @@ class WForm:
             W[15 + p] = self.diag_pp(i, j)
             W[21 + p] = self.diag_pm(i, j)
         return W
+
+    def _eps_staple(self, i):
+        """sum_{jk} eps_ijk sigma_j (x) (U_k(x) U_i(x+k) U_k(x+i)^dag - U_k(x-k)^dag U_i(x-k) U_k(x-k+i)),
+        the staple sum inside the c_5 part of D_i (Sec. 2.2, W+_i), as a 6x6 half-space block."""
+        U = self.U
+        Ui = link(U, i)
+        stap = 0.0
+        for j in range(3):
+            for k in range(3):
+                e = _eps(i, j, k)
+                if e == 0:
+                    continue
+                Uk = link(U, k)
+                up = Uk @ shift(Ui, k, 1) @ dag(shift(Uk, i, 1))
+                dn = dag(shift(Uk, k, -1)) @ shift(Ui, k, -1) @ shift(shift(Uk, k, -1), i, 1)
+                stap = stap + e * kron2(SIGMA[j], up - dn)
+        return stap
 
     def diag_pp(self, i, j):
         """W++_ij = [[0, S], [S, 0]], S = c2/(2u0) (s_i + s_j)(U_i(x) U_j(x+i) + U_j(x) U_i(x+j))."""

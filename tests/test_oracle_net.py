@@ -101,3 +101,41 @@ def test_adam_step_matches_definition():
     p2, m2, v2 = net.adam_step(p, g, m, v, 1, 0.01)
     # first step of Adam moves each real coordinate by lr * sign(gradient)
     assert np.allclose(p2, p - 0.01 * (np.sign(g.real) + 1j * np.sign(g.imag)), atol=1e-6)
+
+
+def test_adam_steps_two_and_three_closed_forms():
+    """Adam (Kingma & Ba) on gradient sequences whose moments have closed forms.
+
+    Per real coordinate with real gradient G_t (twice the Wirtinger gradient):
+      constant G:           every step moves by lr sign(G) (bias corrections exact);
+      G, -G, G:             step 2 moves by -lr (1-b1)/(1+b1) sign(G),
+                            step 3 by lr (1-b1+b1^2)/(1+b1+b1^2) sign(G)  (v^ = G^2 exactly);
+      G, 3G:                step 2 moves by lr ((3+b1)/(1+b1)) / sqrt((9+b2)/(1+b2)) sign(G).
+    Derived by hand from m_t = b1 m + (1-b1) G_t, v_t = b2 v + (1-b2) G_t^2 and the
+    bias-corrected ratio, not by rerunning the recurrence."""
+    b1, b2, lr = 0.9, 0.999, 0.01
+    G = np.array([0.4, -0.7, 0.25, -1.3])
+    seq = [np.array([1.0, -1.0, 1.0]), np.array([1.0, 1.0, 1.0]), np.array([1.0, 3.0, 3.0]),
+           np.array([1.0, -1.0, 1.0])]
+    # coordinates: re/im of two complex parameters
+    g_at = lambda t: np.array([G[0] * seq[0][t] + 1j * G[1] * seq[1][t],
+                               G[2] * seq[2][t] + 1j * G[3] * seq[3][t]]) / 2.0
+    p = np.array([0.3 - 0.2j, -1.0 + 0.5j])
+    m = np.zeros(2, complex)
+    v = np.zeros(2, complex)
+    moves = []
+    for t in range(3):
+        p2, m, v = net.adam_step(p, g_at(t), m, v, t + 1, lr, b1, b2, 1e-8)
+        d = (p - p2) / lr               # update / lr, per real coordinate
+        moves.append(np.array([d[0].real, d[0].imag, d[1].real, d[1].imag]))
+        p = p2
+    sg = np.sign(G)
+    alt2 = -(1 - b1) / (1 + b1)
+    alt3 = (1 - b1 + b1 ** 2) / (1 + b1 + b1 ** 2)
+    grow2 = ((3 + b1) / (1 + b1)) / np.sqrt((9 + b2) / (1 + b2))
+    tol = 1e-6
+    for t in range(3):
+        assert abs(moves[t][1] - sg[1]) < tol                      # constant
+    assert abs(moves[1][0] - alt2 * sg[0]) < tol and abs(moves[2][0] - alt3 * sg[0]) < tol
+    assert abs(moves[1][3] - alt2 * sg[3]) < tol and abs(moves[2][3] - alt3 * sg[3]) < tol
+    assert abs(moves[1][2] - grow2 * sg[2]) < tol

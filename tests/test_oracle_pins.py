@@ -478,3 +478,191 @@ def test_local_window_evaluation_matches_global():
     loc = apply_at_sites(U, psi, c, sites)
     for n, (x, y, z, t) in enumerate(sites):
         assert np.max(np.abs(loc[n] - full[t, z, y, x])) < 1e-13 * np.max(np.abs(full))
+
+
+# --- P9 cubic rotations and spatial parity ---------------------------------------
+# A lattice symmetry maps site x to R x and acts on spin by S with
+# S gamma_nu S^-1 = sum_mu R_{mu nu} gamma_mu (the textbook spinor representation of
+# a rotation or reflection of the lattice).  The transformed fields are
+# psi'(x) = S psi(R^-1 x) and U'_mu(x) = the link of the original lattice from
+# R^-1 x to R^-1 x + R^-1 mu-hat (a daggered backward link when R^-1 mu-hat = -nu-hat).
+# An action invariant under the symmetry satisfies M[U'] psi' = (M[U] psi)'.
+# Unlike gauge covariance, gamma5-hermiticity or translations, this fixes which
+# Pauli matrix goes with which direction in every term (the sigma_i of S_i, the
+# sigma_j of the c_5 staple term, sigma_i +- sigma_j on the diagonals) and the
+# relative sign of forward and backward paths.
+
+def _r_inverse(kind, a=None, b=None):
+    """Coordinates of R^-1 x and the 4x4 matrix R for a 90-degree rotation
+    R e_a = e_b, R e_b = -e_a (kind 'rot'), or spatial parity (kind 'par')."""
+    R = np.eye(4)
+    if kind == "rot":
+        R[:, a] = 0.0
+        R[:, b] = 0.0
+        R[b, a] = 1.0
+        R[a, b] = -1.0
+    else:
+        R[:3, :3] = -np.eye(3)
+    Rinv = np.round(np.linalg.inv(R)).astype(int)
+    return R, Rinv
+
+
+def _spin_matrix(kind, a=None, b=None):
+    g = basis.GAMMA
+    if kind == "rot":
+        return (np.eye(4) - g[a] @ g[b]) / np.sqrt(2.0)
+    return g[3].copy()
+
+
+def _transform(dims, kind, a=None, b=None):
+    """Returns (links map U -> U', spinor map psi -> psi') of the symmetry."""
+    R, Rinv = _r_inverse(kind, a, b)
+    xs = _coords(dims)                                   # [x, y, z, t] over (Lt, Lz, Ly, Lx)
+    src = [sum(Rinv[m, n] * xs[n] for n in range(4)) for m in range(4)]
+
+    def gather(f, shift_vec=(0, 0, 0, 0)):
+        idx = [np.mod(src[m] + shift_vec[m], dims[m]) for m in range(4)]
+        return f[idx[3], idx[2], idx[1], idx[0]]
+
+    S = _spin_matrix(kind, a, b)
+
+    def links(U):
+        out = np.empty_like(U)
+        for mu in range(4):
+            d = Rinv[:, mu]                              # R^-1 mu-hat = +-nu-hat
+            nu = int(np.flatnonzero(d)[0])
+            if d[nu] > 0:
+                out[..., mu, :, :] = gather(U[..., nu, :, :])
+            else:
+                back = [0, 0, 0, 0]
+                back[nu] = -1
+                out[..., mu, :, :] = dag(gather(U[..., nu, :, :], back))
+        return out
+
+    def spinor(psi):
+        return smul(S, gather(psi))
+    return links, spinor, R, S
+
+
+SYMMETRIES = [("rot", 0, 1), ("rot", 0, 2), ("rot", 1, 2), ("par", None, None)]
+DC = (5, 5, 5, 4)    # Lx = Ly = Lz for the rotations
+
+
+@pytest.fixture(scope="module")
+def rough_cubic():
+    return I.random_su3_links(DC, 0.45, 13)
+
+
+def c5_alone(u0):
+    zero = dict(zeta=0.0, r_s=0.0, c_B=0.0, c_E=0.0, c_EE=0.0, c_1=0.0, c_2=0.0, c_3=0.0, c_4=0.0, c_5=0.5)
+    return I.standin_coeffs(m0=0.5, u0=u0, **zero)
+
+
+@pytest.mark.parametrize("kind,a,b", SYMMETRIES)
+def test_symmetry_spin_matrix_is_textbook(kind, a, b):
+    """S gamma_nu S^-1 = sum_mu R_{mu nu} gamma_mu, S unitary."""
+    _, _, R, S = _transform(DC, kind, a, b)
+    Si = np.linalg.inv(S)
+    assert np.allclose(S @ S.conj().T, np.eye(4), atol=1e-15)
+    for nu in range(4):
+        want = sum(R[mu, nu] * basis.GAMMA[mu] for mu in range(4))
+        assert np.allclose(S @ basis.GAMMA[nu] @ Si, want, atol=1e-15)
+
+
+def _symmetry_error(mk, U, c, kind, a, b, psi):
+    links, spinor, _, _ = _transform(DC, kind, a, b)
+    lhs = mk(links(U), c).apply(spinor(psi))
+    rhs = spinor(mk(U, c).apply(psi))
+    return rel(lhs, rhs)
+
+
+@pytest.mark.parametrize("kind,a,b", SYMMETRIES)
+@pytest.mark.parametrize("route", ["A", "B"])
+@pytest.mark.parametrize("coeffs", ["all", "c5"])
+def test_cubic_rotation_and_parity(rough_cubic, kind, a, b, route, coeffs):
+    """P9 at u0 != 1, where the c_5 staple term T_eps is switched on."""
+    u0 = 0.8712
+    c = all_on(u0=u0) if coeffs == "all" else c5_alone(u0)
+    mk = WForm if route == "A" else OKOperatorB
+    psi = I.gaussian_sources(DC, 1, 30)[0]
+    assert _symmetry_error(mk, rough_cubic, c, kind, a, b, psi) < 1e-13
+
+
+def test_plaquette_and_clover_transform(rough_cubic):
+    """The transformed links are a relabelling: same plaquette, and B_i, E_i map as
+    an axial and a polar vector under parity."""
+    links, _, _, _ = _transform(DC, "par")
+    U2 = links(rough_cubic)
+    assert abs(I.plaquette(U2) - I.plaquette(rough_cubic)) < 1e-14
+    B, E = magnetic_electric(rough_cubic)
+    B2, E2 = magnetic_electric(U2)
+    R, Rinv = _r_inverse("par")
+    xs = _coords(DC)
+    src = [np.mod(sum(Rinv[m, n] * xs[n] for n in range(4)), DC[m]) for m in range(4)]
+    g = lambda f: f[src[3], src[2], src[1], src[0]]
+    for i in range(3):
+        assert np.max(np.abs(B2[i] - g(B[i]))) < 1e-14       # axial: unchanged
+        assert np.max(np.abs(E2[i] + g(E[i]))) < 1e-14       # polar: flips
+
+
+# planted slips in the c_5 staple term, made in BOTH routes at once, so the
+# route A == route B pin cannot see them
+def _staple_variant(U, i, variant):
+    """Variants of the c_5 staple sum of D+_i as (sigma index, colour field) pairs."""
+    from oracle.route_a import _eps
+    out = []
+    for j in range(3):
+        for k in range(3):
+            e = _eps(i, j, k)
+            if e == 0:
+                continue
+            Ui, Uk = link(U, i), link(U, k)
+            up = Uk @ shift(Ui, k, 1) @ dag(shift(Uk, i, 1))
+            dn = dag(shift(Uk, k, -1)) @ shift(Ui, k, -1) @ shift(shift(Uk, k, -1), i, 1)
+            if variant == "sigma_k":
+                out.append((k, e * (up - dn)))
+            elif variant == "plus":
+                out.append((j, e * (up + dn)))
+    return out
+
+
+def _planted_ops(variant):
+    import oracle.route_a as ra
+    import oracle.route_b as rb
+
+    class BadA(ra.WForm):
+        def _eps_staple(self, i):
+            return sum(ra.kron2(basis.SIGMA[s], X) for s, X in _staple_variant(self.U, i, variant))
+
+    class BadB(rb.OKOperatorB):
+        def _eps_block(self, i):
+            c = self.c
+            pref = 1j * 0.25 * c.c_5 * (c.u0 ** -2 - c.u0 ** -4)
+            X = [0.0, 0.0, 0.0]
+            for s, C in _staple_variant(self.U, i, variant):
+                X[s] = X[s] + pref * C
+            return X
+    return BadA, BadB
+
+
+@pytest.mark.parametrize("variant", ["sigma_k", "plus"])
+def test_planted_staple_slip_is_caught_by_symmetry(rough_cubic, variant):
+    """A slip shared by both routes passes route A == route B, gauge covariance and
+    gamma5-hermiticity, and is caught by the rotation/parity pin."""
+    BadA, BadB = _planted_ops(variant)
+    c = all_on(u0=0.8712)
+    U = rough_cubic
+    psi, phi = I.gaussian_sources(DC, 2, 31)
+    assert rel(BadA(U, c).apply(psi), BadB(U, c).apply(psi)) < 1e-13          # P3 blind
+    assert rel(BadB(U, c).apply(psi), OKOperatorB(U, c).apply(psi)) > 1e-5     # it is a real change
+    g = I.random_su3_field(DC, I.SEED_GAUGE)
+    U2 = I.gauge_transform_links(U, g)
+    assert rel(BadB(U2, c).apply(cmul(g, psi)), cmul(g, BadB(U, c).apply(psi))) < 1e-13   # P4 blind
+    g5 = lambda f: smul(basis.GAMMA5, f)
+    bad = BadB(U, c)
+    lhs, rhs = vdot(phi, g5(bad.apply(g5(psi)))), vdot(bad.apply(phi), psi)
+    assert abs(lhs - rhs) / abs(rhs) < 1e-13                                   # P5 blind
+    worst = {}
+    for mk, name in [(BadA, "A"), (BadB, "B")]:
+        worst[name] = max(_symmetry_error(mk, U, c, kind, a, b, psi) for kind, a, b in SYMMETRIES)
+    assert worst["A"] > 1e-5 and worst["B"] > 1e-5, worst
