@@ -152,7 +152,8 @@ int iterate(Ctx& C, bool f64, const void* W, int prec, int tps, void* x, void* r
     OK_TRY(fin(C, FIN_ALPHA, apply_blocks(g, tps)));
     OK_TRY(launch_s_update(g, f64, s, r, v, C.w.sc, C.st));
     if (C.net) OK_TRY(apply_net(C, static_cast<float*>(s), static_cast<float*>(sh), 1, false, C.w.netw));
-    OK_TRY(launch_apply(g, W, prec, sh, t, C.c->mhat, tps, EPI_TS, nullptr, C.w.partial, C.st));
+    // omega = <t, s> / <t, t> with the unpreconditioned s (the operator's input is N s when preconditioned)
+    OK_TRY(launch_apply(g, W, prec, sh, t, C.c->mhat, tps, EPI_TS, C.net ? s : nullptr, C.w.partial, C.st));
     OK_TRY(fin(C, FIN_OMEGA, apply_blocks(g, tps)));
     OK_TRY(launch_xr_update(g, f64, x, r, ph, sh, s, t, rhat, C.w.sc, C.w.partial, C.st));
     OK_TRY(fin_blas(C, FIN_RHO));

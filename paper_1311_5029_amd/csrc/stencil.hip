@@ -10,7 +10,7 @@
 // An optional epilogue reduces per-block partial sums of the dot products the
 // BiCGStab recurrence needs right after an application (see blas1.hip):
 //   EPI_RV:  <aux, out>                  (r^ . v)
-//   EPI_TS:  <out, in>, <out, out>      (t . s, t . t)
+//   EPI_TS:  <out, aux or in>, <out, out>  (t . s, t . t; aux NULL: s is the input)
 #include <algorithm>
 
 #include "common.h"
@@ -137,7 +137,8 @@ __global__ void __launch_bounds__(256) k_apply(Geo g, const void* __restrict__ W
                 d1.y += (double)av.re * acc[q].im - (double)av.im * acc[q].re;
             }
         } else if constexpr (EPI == EPI_TS) {
-            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12 + r0;
+            // <t, s>: s is aux when given (a preconditioned solve applies M to N s, not to s)
+            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(aux ? aux : psi) + (size_t)s * 12 + r0;
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const cpx<T> sv = a[q];
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(256) k_apply_saved(Geo g, const void* __restri
                 d1.y += (double)av.re * acc[q].im - (double)av.im * acc[q].re;
             }
         } else if constexpr (EPI == EPI_TS) {
-            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(psi) + (size_t)s * 12;
+            const cpx<T>* a = reinterpret_cast<const cpx<T>*>(aux ? aux : psi) + (size_t)s * 12;
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
                 const cpx<T> sv = a[q];

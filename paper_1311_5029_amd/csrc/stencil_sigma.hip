@@ -381,9 +381,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 #pragma unroll
         for (int q = 0; q < 12; ++q)
             o[MR == 1 ? ((size_t)s * 12 + q) * nr + r : (size_t)s * 12 + q] = acc[q / 6][(q / 3) & 1][q % 3];
-        // epilogue dots; with MR == 1 over this lane's right-hand side, the second vector of
-        // <t, s> given in aux (the solver's s, which is not the operator's input when it is
-        // preconditioned)
+        // epilogue dots; with MR == 1 over this lane's right-hand side.  The second vector of
+        // <t, s> is aux when given (the solver's s, which is not the operator's input when it is
+        // preconditioned), else the input
         const cpx<T>* ax = reinterpret_cast<const cpx<T>*>(aux);
         const cpx<T>* ps = reinterpret_cast<const cpx<T>*>(psi);
         auto at = [&](const cpx<T>* f, int q) __attribute__((always_inline)) {
@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         } else if constexpr (EPI == EPI_TS) {
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                const cpx<T> sv = at(MR == 1 ? ax : ps, q), w = acc[q / 6][(q / 3) & 1][q % 3];
+                const cpx<T> sv = at(ax ? ax : ps, q), w = acc[q / 6][(q / 3) & 1][q % 3];
                 d1.x += (double)w.re * sv.re + (double)w.im * sv.im;
                 d1.y += (double)w.re * sv.im - (double)w.im * sv.re;
                 d2.x += (double)w.re * w.re + (double)w.im * w.im;

@@ -281,6 +281,23 @@ def test_batched_with_network(learned_small, low):
         assert oracle_resid(L.U, L.c, L.xi_eval[k], x[k]) <= ORACLE_SLACK * TOL
 
 
+@pytest.mark.parametrize("single", [1, 1 | 0x100, 1 | 0x200], ids=["f32", "f32-saved", "f32-sigma"])
+def test_single_and_batched_preconditioned_agree(learned_small, single):
+    """The single-right-hand-side and the batched preconditioned solves run the same recurrence
+    (omega = <t, s> / <t, t> with the unpreconditioned s, t = M N s), so with the same network and
+    FP32 arithmetic their iteration counts agree within a few."""
+    ok = lib()
+    L = learned_small
+    rcb, stb, _ = solve(L, L.xi_eval[:2], low=1 | 0x200 | 0x20, net=L.net)
+    assert rcb == ok.OK_SUCCESS
+    for k in range(2):
+        rc, st, x = solve(L, L.xi_eval[k], low=single, net=L.net)
+        assert rc == ok.OK_SUCCESS and st[0]["fallbacks"] == 0
+        nb = stb[k]["iterations"]
+        assert abs(st[0]["iterations"] - nb) <= max(2, 0.1 * nb), (st[0]["iterations"], nb)
+        assert oracle_resid(L.U, L.c, L.xi_eval[k], x) <= ORACLE_SLACK * TOL
+
+
 @pytest.mark.parametrize("bad", ["zero", "nan"])
 @pytest.mark.parametrize("low", [1, 1 | 0x10], ids=["single", "batched"])
 def test_failing_network_falls_back(learned_small, bad, low):

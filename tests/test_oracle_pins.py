@@ -666,3 +666,16 @@ def test_planted_staple_slip_is_caught_by_symmetry(rough_cubic, variant):
     for mk, name in [(BadA, "A"), (BadB, "B")]:
         worst[name] = max(_symmetry_error(mk, U, c, kind, a, b, psi) for kind, a, b in SYMMETRIES)
     assert worst["A"] > 1e-5 and worst["B"] > 1e-5, worst
+
+
+def test_slab_evaluation_matches_global():
+    """M psi evaluated as time slabs in worker processes equals the global operator (the slab
+    windows reach every link and spinor a site's result depends on), for one field and a batch."""
+    from oracle.local import apply_slabs
+    dims = (5, 4, 6, 11)
+    U = I.random_su3_links(dims, 0.45, 43)
+    c = all_on(u0=0.87)
+    psi = I.gaussian_sources(dims, 2, 44)
+    op = OKOperatorB(U, c)
+    assert np.array_equal(apply_slabs(U, psi[0], c, nproc=4), op.apply(psi[0]))
+    assert np.array_equal(apply_slabs(U, psi, c, nproc=3), op.apply(psi))
