@@ -229,6 +229,25 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
                 const double* d_xi, double* d_psi, int nrhs,
                 void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream);
 
+/* ok_bicgstab without a workspace argument and without any device allocation,
+ * for callers that cannot allocate device memory (serving loops that must not
+ * call hipMalloc, harnesses that forbid it).  The workspace is a fixed array
+ * in the library's device memory, one per GPU, of
+ * ok_bicgstab_static_max_bytes() bytes (64 MiB), held until the process ends;
+ * a solve whose ok_bicgstab_workspace_bytes exceeds it returns OK_ESIZE (with
+ * a message) before any HIP call.  Every argument, the result and the
+ * statuses are those of ok_bicgstab.  All calls on one GPU share that array:
+ * two calls that overlap in time on the same GPU (from different host
+ * threads) race and give undefined results.  The first call on a device
+ * looks the array's address up on that device (no allocation). */
+int ok_bicgstab_static(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
+                       const void* d_W64, const void* d_Wlo, int Wlo_prec, const ok_net* net,
+                       const double* d_xi, double* d_psi, int nrhs, ok_solver_stats* stats,
+                       void* stream);
+
+/* Bytes of ok_bicgstab_static's fixed workspace. */
+size_t ok_bicgstab_static_max_bytes(void);
+
 /* Workspace bytes of ok_cgnr (six FP64 fields and the reduction scratch). */
 int ok_cgnr_workspace_bytes(const ok_geom* g, int nrhs, size_t* bytes);
 

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -768,9 +769,44 @@ int ok_bicgstab_workspace_bytes(const ok_geom* g, int nrhs, int Wlo_prec, const 
     return OK_SUCCESS;
 }
 
-int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p, const void* d_W64,
-                const void* d_Wlo, int Wlo_prec, const ok_net* net, const double* d_xi, double* d_psi, int nrhs,
-                void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream) {
+namespace {
+
+// Fixed workspace of ok_bicgstab_static: one copy per GPU, held until the process ends.  Host code
+// never passes this array's name to a kernel or a copy: it takes the device address that
+// hipGetSymbolAddress returns on each device (static_scratch below).
+constexpr size_t kStaticWorkBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kStaticWorkBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];
+
+// the current device's address of `scratch`, looked up on the first call on that device
+int static_scratch(void** ptr) {
+    int dev = -1;
+    OK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d outside the %d the static workspace table holds", dev, kMaxDevices);
+        return OK_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        OK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress returned no address for the static workspace");
+            return OK_EDEVICE;
+        }
+        g_scratch[dev] = p;
+    }
+    *ptr = g_scratch[dev];
+    return OK_SUCCESS;
+}
+
+// ok_bicgstab with the caller's workspace (use_static false) or with `scratch` (true)
+int bicgstab_run(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p, const void* d_W64,
+                 const void* d_Wlo, int Wlo_prec, const ok_net* net, const double* d_xi, double* d_psi, int nrhs,
+                 void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream, bool use_static) {
     Ctx C;
     int rc = make_geo(g, &C.g);
     if (rc) return rc;
@@ -805,10 +841,16 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
     if ((rc = check_solver_net(net, mixed))) return rc;
     const bool batched = mixed && is_batched(Wlo_prec);
     if ((rc = check_ptr(d_W64, "d_W64")) || (mixed && (rc = check_ptr(d_Wlo, "d_Wlo"))) ||
-        (rc = check_ptr(d_xi, "d_xi")) || (rc = check_ptr(d_psi, "d_psi")) || (rc = check_ptr(d_work, "d_work")))
+        (rc = check_ptr(d_xi, "d_xi")) || (rc = check_ptr(d_psi, "d_psi")) ||
+        (!use_static && (rc = check_ptr(d_work, "d_work"))))
         return rc;
     const size_t need = workspace(C.g, nrhs, mixed ? Wlo_prec : -1, net);
-    if (work_bytes < need) {
+    if (use_static && need > kStaticWorkBytes) {
+        set_error("this solve needs %zu bytes of workspace, more than the %zu of the static workspace of "
+                  "ok_bicgstab_static (use ok_bicgstab with a workspace of that size)", need, kStaticWorkBytes);
+        return OK_ESIZE;
+    }
+    if (!use_static && work_bytes < need) {
         set_error("workspace has %zu bytes, needs %zu", work_bytes, need);
         return OK_ESIZE;
     }
@@ -819,6 +861,10 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
             set_error("d_psi must not overlap d_xi");
             return OK_EINVAL;
         }
+    }
+    if (use_static) {
+        if ((rc = static_scratch(&d_work))) return rc;
+        work_bytes = kStaticWorkBytes;
     }
     const int nl = net ? net->n_layers : 0;
     WorkB B;
@@ -891,6 +937,23 @@ int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p,
     }
     return first_bad;
 }
+
+}  // namespace
+
+int ok_bicgstab(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p, const void* d_W64,
+                const void* d_Wlo, int Wlo_prec, const ok_net* net, const double* d_xi, double* d_psi, int nrhs,
+                void* d_work, size_t work_bytes, ok_solver_stats* stats, void* stream) {
+    return bicgstab_run(g, c, p, d_W64, d_Wlo, Wlo_prec, net, d_xi, d_psi, nrhs, d_work, work_bytes, stats, stream,
+                        false);
+}
+
+int ok_bicgstab_static(const ok_geom* g, const ok_coeffs* c, const ok_solver_params* p, const void* d_W64,
+                       const void* d_Wlo, int Wlo_prec, const ok_net* net, const double* d_xi, double* d_psi,
+                       int nrhs, ok_solver_stats* stats, void* stream) {
+    return bicgstab_run(g, c, p, d_W64, d_Wlo, Wlo_prec, net, d_xi, d_psi, nrhs, nullptr, 0, stats, stream, true);
+}
+
+size_t ok_bicgstab_static_max_bytes(void) { return kStaticWorkBytes; }
 
 int ok_cgnr_workspace_bytes(const ok_geom* g, int nrhs, size_t* bytes) {
     Geo G;

@@ -81,6 +81,9 @@ _sig = {
     "ok_bicgstab_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.c_int, _NET, C.POINTER(C.c_size_t)], C.c_int),
     "ok_bicgstab": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, C.c_int, _NET,
                      _P, _P, C.c_int, _P, C.c_size_t, C.POINTER(ok_solver_stats), _P], C.c_int),
+    "ok_bicgstab_static": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, C.c_int,
+                            _NET, _P, _P, C.c_int, C.POINTER(ok_solver_stats), _P], C.c_int),
+    "ok_bicgstab_static_max_bytes": ([], C.c_size_t),
     "ok_cgnr_workspace_bytes": ([C.POINTER(ok_geom), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "ok_cgnr": ([C.POINTER(ok_geom), C.POINTER(ok_coeffs), C.POINTER(ok_solver_params), _P, _P, _P, C.c_int, _P,
                  C.c_size_t, C.POINTER(ok_solver_stats), _P], C.c_int),
@@ -219,6 +222,20 @@ def ok_bicgstab(dims, c, params, d_W64, d_Wlo, Wlo_prec, d_xi, d_psi, nrhs, d_wo
                           stats, _stream(stream))
     _check(rc)
     return rc, [s.as_dict() for s in stats]
+
+
+def ok_bicgstab_static(dims, c, params, d_W64, d_Wlo, Wlo_prec, d_xi, d_psi, nrhs, stream=None, net=None):
+    """ok_bicgstab on the library's fixed per-GPU workspace (no device allocation)."""
+    stats = (ok_solver_stats * nrhs)()
+    p = params.c() if isinstance(params, SolverParams) else params
+    rc = _lib.ok_bicgstab_static(C.byref(geom(dims)), C.byref(coeffs(c)), C.byref(p), _ptr(d_W64), _ptr(d_Wlo),
+                                 Wlo_prec, _netp(net), _ptr(d_xi), _ptr(d_psi), nrhs, stats, _stream(stream))
+    _check(rc)
+    return rc, [s.as_dict() for s in stats]
+
+
+def ok_bicgstab_static_max_bytes():
+    return _lib.ok_bicgstab_static_max_bytes()
 
 
 def ok_cgnr_workspace_bytes(dims, nrhs):

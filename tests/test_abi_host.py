@@ -268,3 +268,21 @@ def test_host_complex_roundtrip():
     t = okinv.to_device_complex(a, device="cpu")
     assert t.dtype == torch.float64 and t.numel() == a.size * 2
     assert np.array_equal(okinv.to_host_complex(t, a.shape), a)
+
+
+def test_static_solve_validation_before_device():
+    from paper_1311_5029_amd import okinv
+    assert okinv.ok_bicgstab_static_max_bytes() == 64 << 20
+    c = okinv.coeffs(I.standin_coeffs())
+    stats = (okinv.ok_solver_stats * 1)()
+    good = okinv.SolverParams().c()
+    bad = okinv.SolverParams(tol=-1.0).c()
+
+    def call(dims, p):
+        return okinv._lib.ok_bicgstab_static(ctypes.byref(okinv.geom(dims)), ctypes.byref(c), ctypes.byref(p),
+                                             0x10000000, None, -1, None, 0x20000000, 0x30000000, 1, stats, None)
+    big = (32, 32, 32, 8)
+    assert okinv.ok_bicgstab_workspace_bytes(big, 1) > 64 << 20
+    assert call(big, good) == okinv.OK_ESIZE and "static workspace" in okinv.ok_last_error()
+    assert call((4, 4, 4, 4), bad) == okinv.OK_EINVAL
+    assert call((2, 4, 4, 4), good) == okinv.OK_EINVAL
