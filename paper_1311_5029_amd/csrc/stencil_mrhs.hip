@@ -9,7 +9,8 @@
 // buffered), and each wavefront runs the GEMMs of 8 sites with operands read
 // from LDS (W) and L2 (neighbour spinors).
 //
-// FP32 W (v_mfma_f32_16x16x4f32, 12 instructions per site and offset):
+// FP32 W (v_mfma_f32_16x16x4f32, 12 instructions per site and offset; the site-major kernel
+// below forms the complex product from three real ones, 9 instructions):
 //   C_r += A_r B_r - A_i B_i,  C_i += A_r B_i + A_i B_r,
 //   M index = output component (12 of 16), N = right-hand side (nrhs of 16),
 //   K step q, lane group g  <->  input component 3g + q.
@@ -306,14 +307,15 @@ __device__ __forceinline__ void load_ops(Ops<P>& o, const uint4* __restrict__ wk
 }
 
 template <int P>
-__device__ __forceinline__ void mma_ops(const Ops<P>& o, int l16, int grp, v4f& acc0, v4f& acc1) {
+__device__ __forceinline__ void mma_ops(const Ops<P>& o, int l16, int grp, v4f& acc0, v4f& acc1, v4f& acc2) {
     if constexpr (P == OK_F32) {
+        // three real products per complex product (Gauss): acc0 += Re a Re b, acc1 += Im a Im b,
+        // acc2 += (Re a + Im a)(Re b + Im b); Re = acc0 - acc1, Im = acc2 - acc0 - acc1 at the end
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[q].x, o.b[q].x, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[q].x, o.b[q].y, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-o.a[q].y, o.b[q].y, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[q].y, o.b[q].x, acc1, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[q].y, o.b[q].y, acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[q].x + o.a[q].y, o.b[q].x + o.b[q].y, acc2, 0, 0, 0);
         }
     } else {
         v8bf bhi, blo;
@@ -388,7 +390,7 @@ __global__ void __launch_bounds__(256) k_apply_site(Geo g, const uint4* __restri
             const int nb = neighbour(g, x, y, z, t, off_d(k, 0), off_d(k, 1), off_d(k, 2), off_d(k, 3));
             load_ops<P, SL>(ring[k], ws + k * CH, spin(nb), lo, l16, grp);
         }
-        v4f acc0 = v4f{0.f, 0.f, 0.f, 0.f}, acc1 = v4f{0.f, 0.f, 0.f, 0.f};
+        v4f acc0 = v4f{0.f, 0.f, 0.f, 0.f}, acc1 = v4f{0.f, 0.f, 0.f, 0.f}, acc2 = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < kW; ++k) {
             const Ops<P> cur = ring[k % DEPTH];
@@ -397,7 +399,7 @@ __global__ void __launch_bounds__(256) k_apply_site(Geo g, const uint4* __restri
                 const int nb = neighbour(g, x, y, z, t, off_d(kn, 0), off_d(kn, 1), off_d(kn, 2), off_d(kn, 3));
                 load_ops<P, SL>(ring[k % DEPTH], ws + kn * CH, spin(nb), lo, l16, grp);
             }
-            mma_ops<P>(cur, l16, grp, acc0, acc1);
+            mma_ops<P>(cur, l16, grp, acc0, acc1, acc2);
         }
         if (!jlive) continue;
         // out = mhat psi + acc
@@ -407,7 +409,8 @@ __global__ void __launch_bounds__(256) k_apply_site(Geo g, const uint4* __restri
                 for (int r = 0; r < 4; ++r) {
                     const size_t i = sp_index<SL>(nrhs, V, l16, s, 4 * grp + r);
                     const float2 c = ps[i];
-                    po[i] = make_float2(mhat * c.x + acc0[r], mhat * c.y + acc1[r]);
+                    const float re = acc0[r] - acc1[r], im = acc2[r] - acc0[r] - acc1[r];
+                    po[i] = make_float2(mhat * c.x + re, mhat * c.y + im);
                 }
             }
         } else {
