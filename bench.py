@@ -10,10 +10,12 @@ with the chosen storage of W (FP32 by default), which runs the MFMA kernel
 (one launch for the 12 right-hand sides).  The metric is the HBM throughput of
 that application in algorithmic bytes (the dense W streamed once + 12 spinors
 read and 12 written, per site), timed with HIP events on the stream the
-library launches on.  The second half of the
-metric, time to ||xi - M psi||/||xi|| <= 1e-10, is measured on the same batch:
-"plain" = FP64 BiCGStab, one right-hand side after the other; "chosen" =
-BiCGStab in FP32 fields with BF16 W and FP64 reliable updates.
+library launches on.  The second half of the metric, time to
+||xi - M psi||/||xi|| <= 1e-10, is measured on the same batch: "plain" = FP64
+BiCGStab with 27 dense FP64 blocks, one right-hand side after the other;
+"chosen" = the fastest of the other solve forms (median of three solves each),
+each reported with its solution's error against the plain FP64 solution and the
+HBM roofline fraction of the whole solve (solve_bytes below).
 
 Prints one JSON line.  --gpus N > 1 is refused (single-GPU build).
 """
@@ -199,35 +201,113 @@ def summarize_trace(d, out_path, command):
     print("\n".join(lines))
 
 
-def cpu_baseline():
-    """The FP64 oracle (operator composition from the links) on a bounded sample:
-    the full 20^3 spatial volume over 32 of the 64 time slices, one application,
-    one thread."""
+# Algorithmic bytes per site of the operator forms a solve launches (W read once + spinor in and out)
+W_SITE = {"f64": 27 * 144 * 16, "f64_sigma": 46 * 9 * 16, "f32": 27 * 144 * 8, "f32_sigma": 46 * 9 * 8,
+          "bf16": 27 * 144 * 4}
+FIELD_PASSES_PER_ITER = 20   # BLAS-1 and operator field reads/writes per BiCGStab iteration and RHS
+UPDATE_FIELD_PASSES = 12     # FP64 field passes of one reliable update (accumulate, residual, cast, restart)
+
+
+def solve_bytes(form, stats):
+    """Algorithmic HBM bytes per site of a whole solve, from its kernel sequence (csrc/solver.cpp):
+    per BiCGStab iteration two operator applications (W once each) and 20 field passes per
+    right-hand side (p update 4, s update 3, x/r update with its dots 7, the two operators' input,
+    output and epilogue-dot fields 6); per reliable update one FP64 application (the sigma-layout
+    FP64 W is read once per four right-hand sides) and 12 FP64 field passes; plus the final FP64
+    check.  Batched forms iterate all 12 right-hand sides until the last converges, so their
+    iteration count is the largest per-column one."""
+    f = form["kind"]
+    nrhs = NRHS
+    its = [s["iterations"] for s in stats]
+    ups = sum(s["reliable_updates"] for s in stats)
+    w64 = W_SITE["f64_sigma" if form["w64_sigma"] else "f64"]
+    if f == "plain":
+        return sum(its) * (2 * w64 + FIELD_PASSES_PER_ITER * 192) + nrhs * (w64 + 4 * 192)
+    wlo = W_SITE[form["wlo"]]
+    fb = 96   # FP32 fields
+    upd = UPDATE_FIELD_PASSES * 192
+    if f == "mixed":
+        return sum(its) * (2 * wlo + FIELD_PASSES_PER_ITER * fb) + ups * (w64 + upd) + nrhs * (w64 + 4 * 192)
+    # batched: one W read per operator application for the whole group
+    groups_w64 = (ups + 3) // 4 if form["w64_sigma"] else ups
+    return (max(its) * (2 * wlo + FIELD_PASSES_PER_ITER * fb * nrhs) + groups_w64 * w64 + ups * upd
+            + nrhs * (w64 + 4 * 192))
+
+
+def host_record():
+    """nproc, usable cores, CPU model and RAM of the host this runs on."""
+    rec = {"nproc": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    rec["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    rec["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return rec
+
+
+def cpu_baseline(plain_iterations=None):
+    """The FP64 oracle (route B, the operator composed from the links) on the bench's own
+    workload: one application of M to the 12 point-source-shaped right-hand sides at
+    20^3 x 64, evaluated as time slabs in one worker process per usable core (at most 16),
+    with NumPy's own threads limited to one per worker.  Also the full oracle BiCGStab solve
+    of the 4^4 configuration, and the oracle's 16^3 x 32 time to solution extrapolated from
+    its measured application time."""
     from threadpoolctl import threadpool_limits
 
+    from oracle.bicgstab import bicgstab
+    from oracle.local import apply_slabs
     from oracle.route_b import OKOperatorB
     from paper_1311_5029_amd import inputs as I
-    dims = (20, 20, 20, 32)
-    U = I.random_su3_links(dims, I.config_epsilon("plaq0.6"), I.SEED_LINKS + 3)
-    c = I.standin_coeffs(m0=0.5, u0=I.tadpole_u0(U))
-    psi = I.gaussian_sources(dims, 1, I.SEED_SOURCES + 3)[0]
+    host = host_record()
+    nproc = max(1, min(16, host["usable_cores"]))
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+    cfg = I.make_config("batched_20x20x20x64", with_sources=False)
+    U, c = cfg["U"], cfg["coeffs"]
+    psi = I.gaussian_sources(DIMS, NRHS, I.SEED_SOURCES + 3)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        op = OKOperatorB(U, c)
-        t1 = time.perf_counter()
-        op.apply(psi)
-        t2 = time.perf_counter()
-    sites = int(np.prod(dims))
-    sps = sites / (t2 - t1)
-    return {
-        "value": round(sps * BYTES_SITE[1] / 1e9, 4),
-        "unit": "GB/s (FP32 W-form algorithmic bytes equivalent)",
-        "cores": 1,
+        apply_slabs(U, psi, c, nproc=nproc)
+        t_apply = time.perf_counter() - t0
+        # C1: the whole oracle solve at 4^4
+        c1 = I.make_config("dense_4x4x4x4")
+        op1 = OKOperatorB(c1["U"], c1["coeffs"])
+        t0 = time.perf_counter()
+        _, info = bicgstab(op1.apply, c1["xi"][0], tol=1e-10)
+        t_c1 = time.perf_counter() - t0
+        # C2: one oracle application at 16^3 x 32 (slab-parallel), times 2 per iteration
+        c2 = I.make_config("mixed_16x16x16x32")
+        t0 = time.perf_counter()
+        apply_slabs(c2["U"], c2["xi"][0], c2["coeffs"], nproc=nproc)
+        t_c2 = time.perf_counter() - t0
+    sites = NRHS * V
+    out = {
+        "value": round(BYTES_STEP[1] * V / t_apply / 1e9, 4),
+        "unit": "GB/s (the bench's algorithmic bytes for the same 12-RHS application / the oracle's time)",
+        "cores": nproc,
         "kind": "oracle",
-        "sample": "one M.psi at 20^3x32 (half the 20^3x64 workload), route-B FP64 NumPy, "
-                  "%.1f s apply + %.1f s link setup; %.0f sites/s" % (t2 - t1, t1 - t0, sps),
-        "sites_per_s": round(sps, 1),
+        "sample": "one M.psi on 12 right-hand sides at 20^3x64 (the whole bench workload, one application): "
+                  "route-B FP64 NumPy in %d slab processes, %.2f s including process start and data transfer; "
+                  "%.0f RHS-sites/s" % (nproc, t_apply, sites / t_apply),
+        "rhs_sites_per_s": round(sites / t_apply, 1),
+        "host": host,
+        "c1_4x4x4x4_solve": {"seconds": round(t_c1, 3), "iterations": info["iters"],
+                             "true_rel_resid": info["true_rel_resid"], "threads": 1, "measured": True},
+        "c2_16x16x16x32_seconds_per_iteration": round(2 * t_c2, 3),
     }
+    if plain_iterations:
+        out["extrapolated_plain_solve_seconds"] = round(2 * plain_iterations * V / (sites / t_apply), 1)
+        out["extrapolated_note"] = ("oracle rate x 2 applications x %d BiCGStab iterations (the GPU plain "
+                                    "solve's count over the 12 sources), not run" % plain_iterations)
+    return out
 
 
 def learned(args):
@@ -354,6 +434,8 @@ def learned(args):
         "value_form": min(("batched_bf16_net", "batched_f32_sigma_net"),
                           key=lambda k: summary[k]["seconds_per_source"]),
         "speedup_vs_plain": {k: round(plain / v["seconds_per_source"], 3) for k, v in summary.items()},
+        # what the network adds to the same batched solver, and what it costs to get
+        "learned_gain_vs_same_solver": learned_gain(summary, train_s, pinfo),
         "forms": summary,
         "network": {"layers": 4, "hops": 27, "params_real": ok.ok_net_param_count(4), "precision": "f32",
                     "training_pairs": n_train, "pair_solves": pinfo,
@@ -364,6 +446,20 @@ def learned(args):
         "data": "synthetic: random SU(3) links at plaquette 0.6; stand-in OK coefficients",
     }
     print(json.dumps(out), flush=True)
+
+
+def learned_gain(summary, train_s, pinfo):
+    """Per-source time of the batched FP32 sigma solver without / with the network, the one-time
+    cost of the network (pair solves + training) and the number of sources after which it has
+    paid for itself."""
+    a = summary["batched_f32_sigma"]["seconds_per_source"]
+    b = summary["batched_f32_sigma_net"]["seconds_per_source"]
+    pair_s = float(pinfo.get("seconds", 0.0)) if isinstance(pinfo, dict) else 0.0
+    cost = pair_s + train_s
+    return {"seconds_per_source_without": a, "seconds_per_source_with": b, "ratio": round(a / b, 3),
+            "one_time_seconds": round(cost, 2), "pair_solve_seconds": round(pair_s, 2),
+            "train_seconds": round(train_s, 2),
+            "break_even_sources": (round(cost / (a - b), 1) if a > b else None)}
 
 
 def mixed(args):
@@ -541,8 +637,10 @@ def main():
     Ws = {}
     pre_ms = {}
     SAVED, SIGMA = ok.OK_LAYOUT_SAVED, ok.OK_LAYOUT_SIGMA
-    wforms = [ok.OK_F64, ok.OK_F32, ok.OK_BF16, ok.OK_F32 | SITE, ok.OK_BF16 | SITE,
-              ok.OK_F64 | SAVED, ok.OK_F32 | SAVED, ok.OK_BF16 | SAVED, ok.OK_F64 | SIGMA, ok.OK_F32 | SIGMA]
+    # (the 14-block saved set, OK_LAYOUT_SAVED, is parity-tested but not timed here: it reads as many
+    # lines through L2 as the 27 dense blocks and is no faster)
+    wforms = [ok.OK_F64, ok.OK_F32, ok.OK_BF16, ok.OK_F32 | SITE, ok.OK_BF16 | SITE, ok.OK_F64 | SIGMA,
+              ok.OK_F32 | SIGMA]
     for prec in wforms:
         Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(DIMS, prec))
         scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(DIMS))
@@ -604,7 +702,7 @@ def main():
     # context: one right-hand side (plane W), and the batched forms
     apply_forms = {}
     for prec in (ok.OK_F64, ok.OK_F32, ok.OK_BF16):
-        for lay in (0, SAVED, SIGMA):
+        for lay in (0, SIGMA):
             if lay == SIGMA and prec == ok.OK_BF16:
                 continue
             ms = time_apply(prec | lay, ok.OK_F64 if prec == ok.OK_F64 else ok.OK_F32, 1)
@@ -665,6 +763,12 @@ def main():
                  ("batched_f32_sigma", ok.OK_F32 | SIGMA | INNER, SIGMA, 3,
                   "12 RHS together: FP32 sigma-layout W read once for all of them, FP32 fields, FP64 reliable "
                   "updates (sigma W)"))
+        kinds = {"plain": dict(kind="plain", w64_sigma=False), "plain_sigma": dict(kind="plain", w64_sigma=True),
+                 "batched_bf16": dict(kind="batched", wlo="bf16", w64_sigma=False),
+                 "batched_bf16_sigma64": dict(kind="batched", wlo="bf16", w64_sigma=True),
+                 "mixed_f32_sigma": dict(kind="mixed", wlo="f32_sigma", w64_sigma=True),
+                 "batched_f32_sigma": dict(kind="batched", wlo="f32_sigma", w64_sigma=True)}
+        psi_plain = None
         for name, low, w64, reps, desc in forms:
             lp = -1 if low is None else low
             work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(DIMS, NRHS, lp))
@@ -679,14 +783,27 @@ def main():
                 torch.cuda.synchronize()
                 secs.append(time.perf_counter() - t)
             sec = float(np.median(secs))
+            nbytes = solve_bytes(kinds[name], st) * V
             res[name] = {
                 "form": desc, "seconds": round(sec, 3), "status": rc, "repeats": reps,
                 "iterations": int(sum(s["iterations"] for s in st)),
+                "iterations_max_rhs": int(max(s["iterations"] for s in st)),
                 "matvec_f64": int(sum(s["matvec_hi"] for s in st)),
                 "matvec_low": int(sum(s["matvec_lo"] for s in st)),
                 "reliable_updates": int(sum(s["reliable_updates"] for s in st)),
                 "max_true_rel_resid": max(s["true_rel_resid"] for s in st),
+                "roofline": {"algorithmic_bytes": nbytes, "GB/s": round(nbytes / sec / 1e9, 1),
+                             "frac": round(nbytes / sec / 1e9 / HBM_PEAK_GBS, 4)},
             }
+            # error of this form's solution against the plain FP64 one (whose residual the oracle
+            # checks in the full-size tests), per right-hand side
+            if psi_plain is None:
+                psi_plain = psi.clone()
+            else:
+                d = (psi - psi_plain).view(NRHS, -1)
+                errs = (torch.linalg.vector_norm(d, dim=1) /
+                        torch.linalg.vector_norm(psi_plain.view(NRHS, -1), dim=1)).tolist()
+                res[name]["rel_error_vs_plain_f64"] = {"max": max(errs), "median": float(np.median(errs))}
             log("solve %s: %s" % (name, res[name]))
             del work, psi
         # CG on the normal equations (ok_cgnr, sigma-layout FP64 W) on the first two sources, per source,
@@ -713,19 +830,14 @@ def main():
         solve = {"workload": "12 point sources to ||xi-M psi||/||xi|| <= 1e-10 (FP64 true residual)",
                  "plain": res["plain"], "chosen": dict(name=best, **res[best]),
                  "speedup": round(res["plain"]["seconds"] / res[best]["seconds"], 3),
+                 # the best unpreconditioned FP64 form (sigma-layout W), for scale
+                 "speedup_vs_plain_sigma": round(res["plain_sigma"]["seconds"] / res[best]["seconds"], 3),
                  "forms": res, "cgnr": cg}
 
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline()
-        if solve is not None:
-            # the oracle's time for the plain solve of the 12 sources at 20^3x64: its per-site
-            # application rate x 2 applications per iteration x the plain solve's iterations
-            its = solve["plain"]["iterations"]
-            cpu["extrapolated_plain_solve_seconds"] = round(2 * its * V / cpu["sites_per_s"], 1)
-            cpu["extrapolated_note"] = ("oracle M.psi rate x 2 x %d BiCGStab iterations (the GPU plain solve's "
-                                        "count), not run" % its)
+        cpu = cpu_baseline(solve["plain"]["iterations"] if solve is not None else None)
         log("cpu baseline %s" % cpu)
 
     out = {

@@ -345,3 +345,33 @@ def test_gauge_covariance_on_gpu():
         torch.cuda.synchronize()
         outs.append(ok.to_host_complex(out, f.shape))
     assert rel(outs[1], cmul(g, outs[0])) < 1e-5
+
+
+def test_training_checkpoint_resume_is_bit_identical(nl, tmp_path):
+    """Training interrupted after 7 of 16 steps, checkpointed and resumed from the file gives the
+    same parameters, Adam moments and loss history as the uninterrupted run, bit for bit (the
+    step fixes the mini-batch and the learning rate; the reductions have a fixed order)."""
+    from paper_1311_5029_amd import train as TR
+    ok = nl.ok
+    nf = 8
+    target = I.net_init_params(2, 0.5, 116, noise=0.2)
+    xi = I.gaussian_sources(nl.dims, nf, 117)
+    psi = N.forward(nl.P, target, xi)[-1]
+    d_xi, d_psi = nl.up(xi), nl.up(psi)
+    kw = dict(n_layers=2, steps=16, batch=4, lr=3e-3, log_every=1)
+    full_ck = str(tmp_path / "full.npz")
+    net_a, hist_a = TR.train(nl.dims, nl.T, d_xi, d_psi, nf, 0.5, checkpoint=full_ck, **kw)
+    part_ck = str(tmp_path / "part.npz")
+    TR.train(nl.dims, nl.T, d_xi, d_psi, nf, 0.5, checkpoint=part_ck, stop_after=7, **kw)
+    st = TR.load_checkpoint(part_ck)
+    assert st["step"] == 7 and len(st["history"]) == 7
+    net_b, hist_b = TR.train(nl.dims, nl.T, d_xi, d_psi, nf, 0.5, checkpoint=part_ck, resume=part_ck, **kw)
+    nl.sync()
+    assert hist_a == hist_b
+    assert np.array_equal(net_a.params.cpu().numpy(), net_b.params.cpu().numpy())
+    a, b = TR.load_checkpoint(full_ck), TR.load_checkpoint(part_ck)
+    assert a["step"] == b["step"] == 16
+    for k in ("params", "adam_m", "adam_v"):
+        assert np.array_equal(a[k], b[k]), k
+    with pytest.raises(ValueError):
+        TR.train(nl.dims, nl.T, d_xi, d_psi, nf, 0.5, resume=part_ck, **dict(kw, lr=1e-3))
