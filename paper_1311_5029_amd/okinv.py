@@ -14,6 +14,12 @@ import os
 
 import numpy as np
 
+# torch first: the library then binds to the HIP runtime torch has loaded.  Loaded the other way
+# round, the process holds two HIP and two HSA runtimes (the system's for the library, torch's
+# own for torch), and the second to open the device finds none (HIP error 100 at the library's
+# first launch).
+import torch  # noqa: F401,E402
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libokinv.so")
 if not os.path.exists(LIB_PATH):

@@ -23,7 +23,8 @@ def declared_functions():
 
 
 def test_every_declared_symbol_is_exported():
-    lib = ctypes.CDLL(LIB)
+    from paper_1311_5029_amd import okinv
+    lib = okinv._lib
     names = declared_functions()
     assert len(names) >= 9
     for n in names:
@@ -286,3 +287,17 @@ def test_static_solve_validation_before_device():
     assert call(big, good) == okinv.OK_ESIZE and "static workspace" in okinv.ok_last_error()
     assert call((4, 4, 4, 4), bad) == okinv.OK_EINVAL
     assert call((2, 4, 4, 4), good) == okinv.OK_EINVAL
+
+
+def test_binding_loads_one_hip_runtime():
+    """Importing the binding before torch must not load a second HIP / HSA runtime next to
+    torch's (two runtimes in one process leave the second without a device)."""
+    import subprocess
+    import sys
+    code = ("import paper_1311_5029_amd.okinv, torch\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "libs = sorted(set(l.split()[-1] for l in maps if 'libamdhip64' in l or 'libhsa-runtime64' in l))\n"
+            "print(len([l for l in libs if 'amdhip64' in l]), len([l for l in libs if 'hsa-runtime' in l]))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.split()[-2:] == ["1", "1"], out.stdout
