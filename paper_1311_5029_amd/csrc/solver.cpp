@@ -429,7 +429,8 @@ size_t layout_batched(const Geo& g, int nrhs, int net_layers, char* base, WorkB*
     WorkB tmp;
     WorkB& W = w ? *w : tmp;
     W.sc = reinterpret_cast<ScalB*>(take(sizeof(ScalB)));
-    const int nb = std::max({kGridB, col_blocks(g), sigma_mr_blocks(g, kMaxRhsB)});
+    int nb = std::max(kGridB, col_blocks(g));
+    for (int n = 1; n <= kMaxRhsB; ++n) nb = std::max(nb, sigma_mr_blocks(g, n));
     W.partial = reinterpret_cast<double2*>(take((size_t)nb * kMaxRhsB * 2 * sizeof(double2)));
     W.t64 = reinterpret_cast<double*>(take((size_t)4 * g.V * 12 * 16));   // four FP64 fields
     for (int i = 0; i < (net_layers ? 9 : 7); ++i) W.f[i] = reinterpret_cast<float*>(take((size_t)g.V * 12 * nrhs * 8));

@@ -238,7 +238,7 @@ def test_apply_sigma_f64_columns(lat):
         assert rel(got[k], lat.apply(ok.OK_F64 | SIGMA, psi[k])) <= 1e-15
 
 
-@pytest.mark.parametrize("nrhs", [1, 5, 12, 16])
+@pytest.mark.parametrize("nrhs", [1, 2, 5, 6, 12, 16])
 def test_apply_sigma_rhs_inner_matches_single(lat, nrhs):
     """FP32 sigma W on nrhs right-hand-side-inner fields (the batched solver's operator): every
     right-hand side against the oracle (FP32 bar) and against the one-at-a-time sigma kernel,
