@@ -380,39 +380,54 @@ def learned(args):
         rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10, W64_layout=w64), Ws[ok.OK_F64 | w64],
                                 None if low is None else Ws[low & ~INNER], lp, d_xi, psi, nrhs, work, net=nn)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, rc, st
+        return time.perf_counter() - t0, rc, st, psi.view(nrhs, -1)
 
     forms = {}
 
-    def add(name, sec, rc, st):
-        f = forms.setdefault(name, {"seconds": [], "iterations": [], "status": [], "resid": [], "fallbacks": 0})
+    def add(name, sec, rc, st, psi, ref=None):
+        """ref: the plain FP64 solutions of the same sources ([nrhs][...] device), for the error"""
+        f = forms.setdefault(name, {"seconds": [], "iterations": [], "status": [], "resid": [], "fallbacks": 0,
+                                    "err": []})
         f["seconds"].append(sec)
         f["iterations"].extend(s["iterations"] for s in st)
         f["status"].append(rc)
         f["resid"].extend(s["true_rel_resid"] for s in st)
         f["fallbacks"] += sum(s["fallbacks"] for s in st)
+        if ref is not None:
+            e = torch.linalg.vector_norm(psi - ref, dim=1) / torch.linalg.vector_norm(ref, dim=1)
+            f["err"].extend(e.tolist())
 
     if gauss_eval:
         for j, xi in enumerate(I.gaussian_source_batches(dims, n_eval, I.SEED_EVAL, 16)):
+            plain = []
             for k in range(xi.shape[0]):
-                for name, low, wn in (("plain_f64", None, False), ("mixed_f32", ok.OK_F32, False),
-                                      ("mixed_f32_net", ok.OK_F32, True)):
-                    add(name, *run(xi[k], low, wn, 1))
+                r = run(xi[k], None, False, 1)
+                add("plain_f64", *r)
+                plain.append(r[3])
+                for name, low, wn in (("mixed_f32", ok.OK_F32, False), ("mixed_f32_net", ok.OK_F32, True)):
+                    add(name, *run(xi[k], low, wn, 1), ref=plain[-1])
+            ref = torch.cat(plain)
             for name, wn in (("batched_bf16", False), ("batched_bf16_net", True)):
-                add(name, *run(xi, lowb, wn, xi.shape[0]))
+                add(name, *run(xi, lowb, wn, xi.shape[0]), ref=ref)
             for name, wn in (("batched_f32_sigma", False), ("batched_f32_sigma_net", True)):
-                add(name, *run(xi, lows, wn, xi.shape[0], SIGMA))
+                add(name, *run(xi, lows, wn, xi.shape[0], SIGMA), ref=ref)
+            del plain, ref
             log("evaluated %d/%d: %s" % (min(n_eval, 16 * (j + 1)), n_eval,
                                          {k: (round(float(np.mean(v["iterations"])), 1), round(sum(v["seconds"]), 2))
                                           for k, v in forms.items()}))
     else:
         xi = I.point_sources(dims)
+        plain = []
         for k in range(12):
-            add("plain_f64", *run(xi[k], None, False, 1))
-        add("batched_bf16", *run(xi, lowb, False, 12))
-        add("batched_bf16_net", *run(xi, lowb, True, 12))
-        add("batched_f32_sigma", *run(xi, lows, False, 12, SIGMA))
-        add("batched_f32_sigma_net", *run(xi, lows, True, 12, SIGMA))
+            r = run(xi[k], None, False, 1)
+            add("plain_f64", *r)
+            plain.append(r[3])
+        ref = torch.cat(plain)
+        add("batched_bf16", *run(xi, lowb, False, 12), ref=ref)
+        add("batched_bf16_net", *run(xi, lowb, True, 12), ref=ref)
+        add("batched_f32_sigma", *run(xi, lows, False, 12, SIGMA), ref=ref)
+        add("batched_f32_sigma_net", *run(xi, lows, True, 12, SIGMA), ref=ref)
+        del plain, ref
         log("evaluated: %s" % {k: (round(float(np.mean(v["iterations"])), 1), round(sum(v["seconds"]), 2))
                                for k, v in forms.items()})
 
@@ -424,6 +439,8 @@ def learned(args):
                          "iterations_median": float(np.median(f["iterations"])),
                          "all_converged": all(r == ok.OK_SUCCESS for r in f["status"]),
                          "max_true_rel_resid": max(f["resid"]), "fallbacks": f["fallbacks"]}
+        if f["err"]:   # against the plain FP64 solution of the same source
+            summary[name]["rel_error_vs_plain_f64"] = {"max": max(f["err"]), "median": float(np.median(f["err"]))}
     plain = summary["plain_f64"]["seconds_per_source"]
     out = {
         "metric": "time to 1e-10 residual per source, plain FP64 vs learned preconditioner",
