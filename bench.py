@@ -175,11 +175,12 @@ def summarize_trace(d, out_path, command):
     files = [os.path.join(dp, f) for dp, _, fs in os.walk(d) for f in fs if f.endswith("kernel_stats.csv")]
     rows = list(csv.DictReader(open(files[0])))
     lines = ["# rocprofv3 kernel statistics", "", "command: " + command, "",
-             "%-44s %6s %14s %8s" % ("kernel", "calls", "avg ns", "% time")]
-    for r in rows[:14]:
+             "%-44s %6s %14s %10s %8s" % ("kernel", "calls", "avg ns", "total ms", "% time")]
+    for r in rows[:16]:
         name = r["Name"].replace("okinv::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
         name = re.sub(r"\(.*", "", name).replace("void ", "")[:44]
-        lines.append("%-44s %6s %14.0f %8.2f" % (name, r["Calls"], float(r["AverageNs"]), float(r["Percentage"])))
+        lines.append("%-44s %6s %14.0f %10.2f %8.2f" % (name, r["Calls"], float(r["AverageNs"]),
+                                                        float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
     for kernel, per_site in (("k_apply", BYTES_SITE), ("k_apply_site", BYTES_STEP), ("k_apply_saved", BYTES_SAVED),
                              ("k_apply_sigma", BYTES_SIGMA), ("k_apply_sigma_mr", BYTES_SIGMA_MR)):
         for form, prec in (("f64", 0), ("f32", 1), ("bf16", 2)):
@@ -593,6 +594,46 @@ def net_kernels(args):
     print(json.dumps(out), flush=True)
 
 
+def chosen_solve(args):
+    """The chosen form alone: the 12 point sources at 20^3 x 64 solved together with FP32
+    sigma-layout W and FP64 reliable updates (sigma FP64 W), three times; one JSON line.  Run
+    under rocprofv3 --kernel-trace --stats it gives the solve's time per kernel."""
+    import torch
+
+    from paper_1311_5029_amd import inputs as I
+    from paper_1311_5029_amd import okinv as ok
+
+    torch.cuda.set_device(0)
+    cfg = I.make_config("batched_20x20x20x64")
+    c = cfg["coeffs"]
+    links = ok.to_device_complex(cfg["U"])
+    S, INNER = ok.OK_LAYOUT_SIGMA, ok.OK_SPINOR_RHS_INNER
+    Ws = {}
+    for prec in (ok.OK_F64 | S, ok.OK_F32 | S):
+        Ws[prec] = ok.empty_bytes(ok.ok_W_bytes(DIMS, prec))
+        scr = ok.empty_bytes(ok.ok_precompute_scratch_bytes(DIMS))
+        ok.ok_precompute_W(DIMS, c, links, prec, Ws[prec], scr)
+        del scr
+    xi = ok.to_device_complex(cfg["xi"])
+    lp = ok.OK_F32 | S | INNER
+    work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(DIMS, NRHS, lp))
+    secs = []
+    for _ in range(3):
+        psi = torch.zeros_like(xi)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, st = ok.ok_bicgstab(DIMS, c, ok.SolverParams(tol=1e-10, W64_layout=S), Ws[ok.OK_F64 | S],
+                                Ws[ok.OK_F32 | S], lp, xi, psi, NRHS, work)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t)
+        log("chosen solve %.3f s, status %d" % (secs[-1], rc))
+    print(json.dumps({"metric": "time to 1e-10 residual, 12 point sources at 20^3x64, chosen form",
+                      "seconds": [round(x, 4) for x in secs], "status": rc,
+                      "iterations_largest": max(s["iterations"] for s in st),
+                      "reliable_updates": sum(s["reliable_updates"] for s in st),
+                      "max_true_rel_resid": max(s["true_rel_resid"] for s in st)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -608,7 +649,7 @@ def main():
                     help="write a text summary of a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--workload", default="batched_20x20x20x64",
                     choices=["batched_20x20x20x64", "mixed_16x16x16x32", "learned_24x24x24x64",
-                             "learned_batched_32x32x32x64", "net"],
+                             "learned_batched_32x32x32x64", "net", "chosen_solve_20x20x20x64"],
                     help="batched_20x20x20x64 (default): the M.psi bench line and its solves; "
                          "mixed_16x16x16x32: plain vs mixed precision; learned_*: learned-preconditioner "
                          "solves; net: the network kernels alone")
@@ -629,6 +670,9 @@ def main():
         sys.exit(2)
     if args.workload == "net":
         net_kernels(args)
+        return
+    if args.workload == "chosen_solve_20x20x20x64":
+        chosen_solve(args)
         return
     if args.workload == "mixed_16x16x16x32":
         mixed(args)
