@@ -49,6 +49,11 @@ BYTES_SIGMA_MR = {1: 46 * 9 * 8 + NRHS * 2 * 96}
 BYTES_STEP = {0: NRHS * BYTES_SITE[0], 1: 27 * 144 * 8 + NRHS * 2 * 96, 2: 27 * 144 * 4 + NRHS * 2 * 96}
 PREC_NAME = {0: "f64", 1: "f32", 2: "bf16"}
 KERNEL_NAME = "k_apply"
+# reliable-update threshold of the chosen form (FP32 W): an FP64 update when the FP32 residual has
+# dropped by this factor.  At 20^3x64 (12 point sources) 0.1 / 0.03 / 0.01 / 0.003 / 0.001 / 0.0003
+# gave 0.82 / 0.76 / 0.75 / 0.72 / 0.72 / 0.74 s with 94-98 iterations (the BF16-W forms keep 0.1:
+# their operator is only accurate to ~2^-8, so an FP32 cycle cannot go much deeper).
+CHOSEN_DELTA = 0.003
 
 
 def log(msg):
@@ -622,8 +627,8 @@ def chosen_solve(args):
         psi = torch.zeros_like(xi)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        rc, st = ok.ok_bicgstab(DIMS, c, ok.SolverParams(tol=1e-10, W64_layout=S), Ws[ok.OK_F64 | S],
-                                Ws[ok.OK_F32 | S], lp, xi, psi, NRHS, work)
+        rc, st = ok.ok_bicgstab(DIMS, c, ok.SolverParams(tol=1e-10, delta=CHOSEN_DELTA, W64_layout=S),
+                                Ws[ok.OK_F64 | S], Ws[ok.OK_F32 | S], lp, xi, psi, NRHS, work)
         torch.cuda.synchronize()
         secs.append(time.perf_counter() - t)
         log("chosen solve %.3f s, status %d" % (secs[-1], rc))
@@ -821,19 +826,24 @@ def main():
                                                                        "with the sigma-layout FP64 W"),
                  ("mixed_f32_sigma", ok.OK_F32 | SIGMA, SIGMA, 3, "one RHS after the other: FP32 sigma-layout W, "
                                                                   "FP32 fields, FP64 reliable updates (sigma W)"),
+                 ("batched_f32_sigma_delta0.1", ok.OK_F32 | SIGMA | INNER, SIGMA, 1,
+                  "12 RHS together: FP32 sigma-layout W read once for all of them, FP32 fields, FP64 reliable "
+                  "updates (sigma W) at the default threshold delta = 0.1"),
                  ("batched_f32_sigma", ok.OK_F32 | SIGMA | INNER, SIGMA, 3,
                   "12 RHS together: FP32 sigma-layout W read once for all of them, FP32 fields, FP64 reliable "
-                  "updates (sigma W)"))
+                  "updates (sigma W) when the FP32 residual has dropped by delta = %g" % CHOSEN_DELTA))
         kinds = {"plain": dict(kind="plain", w64_sigma=False), "plain_sigma": dict(kind="plain", w64_sigma=True),
                  "batched_bf16": dict(kind="batched", wlo="bf16", w64_sigma=False),
                  "batched_bf16_sigma64": dict(kind="batched", wlo="bf16", w64_sigma=True),
                  "mixed_f32_sigma": dict(kind="mixed", wlo="f32_sigma", w64_sigma=True),
-                 "batched_f32_sigma": dict(kind="batched", wlo="f32_sigma", w64_sigma=True)}
+                 "batched_f32_sigma": dict(kind="batched", wlo="f32_sigma", w64_sigma=True),
+                 "batched_f32_sigma_delta0.1": dict(kind="batched", wlo="f32_sigma", w64_sigma=True)}
         psi_plain = None
         for name, low, w64, reps, desc in forms:
             lp = -1 if low is None else low
             work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(DIMS, NRHS, lp))
-            params = ok.SolverParams(tol=1e-10, W64_layout=w64)
+            params = ok.SolverParams(tol=1e-10, W64_layout=w64,
+                                     delta=CHOSEN_DELTA if name == "batched_f32_sigma" else 0.1)
             secs = []
             for _ in range(reps):
                 psi = torch.zeros_like(xi)
