@@ -366,7 +366,7 @@ def learned(args):
     lowb = ok.OK_BF16 | SITE
     lows = ok.OK_F32 | SIGMA | INNER   # the fastest batched solve: FP32 sigma W, sigma FP64 reliable updates
     xi32, psi32, pinfo = TR.solve_pairs(dims, c, Ws[ok.OK_F64 | SIGMA], Ws[ok.OK_F32 | SIGMA], lows, n_train,
-                                        I.SEED_TRAIN, log=log, w64_layout=SIGMA)
+                                        I.SEED_TRAIN, log=log, w64_layout=SIGMA, delta=CHOSEN_DELTA)
     torch.cuda.synchronize()
     t = time.perf_counter()
     net, hist = TR.train(dims, T, xi32, psi32, n_train, 1.0 / c.mhat, n_layers=4, steps=args.train_steps,
@@ -383,8 +383,11 @@ def learned(args):
         psi = torch.zeros_like(d_xi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10, W64_layout=w64), Ws[ok.OK_F64 | w64],
-                                None if low is None else Ws[low & ~INNER], lp, d_xi, psi, nrhs, work, net=nn)
+        # the FP32 sigma-layout batched forms run at the chosen form's reliable-update threshold
+        delta = CHOSEN_DELTA if low == lows else 0.1
+        rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10, delta=delta, W64_layout=w64),
+                                Ws[ok.OK_F64 | w64], None if low is None else Ws[low & ~INNER], lp, d_xi, psi, nrhs,
+                                work, net=nn)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, rc, st, psi.view(nrhs, -1)
 

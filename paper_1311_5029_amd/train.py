@@ -15,9 +15,10 @@ from . import inputs as I
 from . import okinv as ok
 
 
-def solve_pairs(dims, c, W64, Wlo, Wlo_prec, n, seed, group=16, tol=1e-10, stream=None, log=None, w64_layout=0):
+def solve_pairs(dims, c, W64, Wlo, Wlo_prec, n, seed, group=16, tol=1e-10, stream=None, log=None, w64_layout=0,
+                delta=0.1):
     """n Gaussian sources (gaussian_source_batches of `seed`, `group` at a time) and their
-    solutions; w64_layout is the layout flag of W64.  Returns (xi32, psi32, info): FP32 device
+    solutions; w64_layout is the layout flag of W64, delta the reliable-update threshold.  Returns (xi32, psi32, info): FP32 device
     fields [n][V][4][3] complex as flat float tensors, and totals of the solves."""
     import torch
     V = I.volume(dims)
@@ -32,7 +33,7 @@ def solve_pairs(dims, c, W64, Wlo, Wlo_prec, n, seed, group=16, tol=1e-10, strea
         psi = torch.zeros_like(d_xi)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=tol, W64_layout=w64_layout), W64, Wlo, Wlo_prec, d_xi,
+        rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=tol, delta=delta, W64_layout=w64_layout), W64, Wlo, Wlo_prec, d_xi,
                                 psi, nb, work, stream)
         torch.cuda.synchronize()
         info["seconds"] += time.perf_counter() - t

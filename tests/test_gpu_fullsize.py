@@ -224,7 +224,8 @@ def test_c4_preconditioned_batched_solve_oracle_residual(c4):
     ok = lib()
     net = _full_net(c4, _small_net("learned_24x24x24x64"))
     xi = I.gaussian_sources(c4.dims, 4, I.SEED_EVAL)
-    rc, st, x = _solve(c4, xi, CHOSEN, SIGMA, net=net)
+    rc, st, x = _solve(c4, xi, CHOSEN, SIGMA, net=net,
+                       group_params=lib().SolverParams(tol=1e-10, delta=0.003))
     assert rc == ok.OK_SUCCESS
     assert all(s["fallbacks"] == 0 and s["net_applies"] > 0 for s in st)
     res = _oracle_resid(c4.U, c4.c, xi[:2], x[:2])
@@ -238,7 +239,8 @@ def test_c5_preconditioned_batched_point_sources_oracle_residual(c5):
     ok = lib()
     net = _full_net(c5, _small_net("learned_batched_32x32x32x64"))
     xi = I.point_sources(c5.dims)
-    rc, st, x = _solve(c5, xi, CHOSEN, SIGMA, net=net)
+    rc, st, x = _solve(c5, xi, CHOSEN, SIGMA, net=net,
+                       group_params=lib().SolverParams(tol=1e-10, delta=0.003))
     assert rc == ok.OK_SUCCESS
     assert all(s["fallbacks"] == 0 and s["net_applies"] > 0 for s in st)
     res = _oracle_resid(c5.U, c5.c, xi[[0, 7]], x[[0, 7]])
