@@ -109,7 +109,9 @@ typedef struct ok_coeffs {
 
 typedef struct ok_solver_params {
     double tol;             /* stop when ||xi - M psi|| / ||xi|| <= tol in FP64 (e.g. 1e-10) */
-    double delta;           /* reliable-update threshold of the low-precision solve (e.g. 0.1) */
+    double delta;           /* reliable-update threshold of the low-precision solve: an FP64
+                               update when the low-precision residual has dropped by this
+                               factor (e.g. 0.1 for BF16 W; FP32 W stays accurate to 0.003) */
     int32_t max_iter;       /* BiCGStab iterations, all restarts included       */
     int32_t max_restarts;   /* restarts after breakdown or residual drift        */
     int32_t zero_guess;     /* 1: start from psi = 0; 0: use d_psi as the guess  */
