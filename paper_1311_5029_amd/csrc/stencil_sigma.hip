@@ -14,9 +14,9 @@
 // (A + B)^dag), the off-diagonal one to -H^dag, and [[0, H], [H, N]] to [[N^dag, -H^dag],
 // [-H^dag, 0]].
 //
-// One thread per site and right-hand side: one right-hand side per thread and site, or
-// several per site (right-hand-side-inner FP32 fields, or up to four separate FP64 fields), the
-// lanes of a site then sharing every matrix load.  Per site and right-hand side: 46 matrices
+// One thread per site, or several per site (right-hand-side-inner FP32 fields, two right-hand
+// sides per thread when their number is even; or up to four separate FP64 fields, one per
+// thread), the lanes of a site then sharing every matrix load.  Per site and right-hand side: 46 matrices
 // (3,312 B FP32, 6,624 B FP64) read at the site and again as the backward blocks of its
 // neighbours, one spinor out, and 27 neighbour spinors (L2 hits mostly); 232 colour
 // matrix-vector products (2,088 complex multiply-adds, against 3,888 for 27 dense blocks).
