@@ -514,7 +514,9 @@ def mixed(args):
            "unit": "s", "forms": {}}
     sol = {}
     for name, low, w64 in (("plain_f64", None, 0), ("mixed_f32", ok.OK_F32, 0), ("mixed_bf16", ok.OK_BF16, 0),
-                           ("plain_f64_sigma", None, SIGMA), ("mixed_f32_sigma", ok.OK_F32 | SIGMA, SIGMA)):
+                           ("plain_f64_sigma", None, SIGMA), ("mixed_f32_sigma", ok.OK_F32 | SIGMA, SIGMA),
+                           ("mixed_f32_sigma_delta0.003", ok.OK_F32 | SIGMA, SIGMA)):
+        delta = CHOSEN_DELTA if name.endswith("_delta0.003") else 0.1
         lp = -1 if low is None else low
         work = ok.empty_bytes(ok.ok_bicgstab_workspace_bytes(dims, 1, lp))
         best = None
@@ -522,8 +524,8 @@ def mixed(args):
             psi = torch.zeros_like(xi)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10, W64_layout=w64), Ws[ok.OK_F64 | w64],
-                                    None if low is None else Ws[low], lp, xi, psi, 1, work)
+            rc, st = ok.ok_bicgstab(dims, c, ok.SolverParams(tol=1e-10, delta=delta, W64_layout=w64),
+                                    Ws[ok.OK_F64 | w64], None if low is None else Ws[low], lp, xi, psi, 1, work)
             torch.cuda.synchronize()
             sec = time.perf_counter() - t
             best = sorted((best or []) + [sec])
@@ -532,7 +534,7 @@ def mixed(args):
                               "reliable_updates": st[0]["reliable_updates"],
                               "true_rel_resid": st[0]["true_rel_resid"]}
         log("%s %s" % (name, out["forms"][name]))
-    for name in ("mixed_f32", "mixed_bf16", "plain_f64_sigma", "mixed_f32_sigma"):
+    for name in ("mixed_f32", "mixed_bf16", "plain_f64_sigma", "mixed_f32_sigma", "mixed_f32_sigma_delta0.003"):
         err = float(torch.linalg.vector_norm(sol[name] - sol["plain_f64"]) /
                     torch.linalg.vector_norm(sol["plain_f64"]))
         out["forms"][name]["rel_error_vs_plain_f64"] = err

@@ -406,8 +406,8 @@ def test_16x16x16x32_sigma_layout_full_size():
     cfg = I.make_config("mixed_16x16x16x32")
     L = Lattice(cfg["dims"], cfg["U"], cfg["coeffs"])
     xi = cfg["xi"][0]
-    for low in (None, ok.OK_F32 | SIGMA):
-        rc, st, x = solve(L, xi, low=low, w64=SIGMA)
+    for low, delta in ((None, 0.1), (ok.OK_F32 | SIGMA, 0.1), (ok.OK_F32 | SIGMA, 0.003)):
+        rc, st, x = solve(L, xi, low=low, w64=SIGMA, params=ok.SolverParams(tol=TOL, delta=delta))
         assert rc == ok.OK_SUCCESS
         assert oracle_resid(cfg["U"], cfg["coeffs"], xi, x) <= ORACLE_SLACK * TOL
 
